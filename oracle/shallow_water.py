@@ -1,0 +1,186 @@
+"""Oracle for the linearised shallow-water system (Section 3 of the paper).
+
+Unknowns per element: (phi, u, v), each in Q^p.  One implicit time step of
+size dt is solved; with a = 2 the implicit operator is the Crank-Nicolson
+one, (2/dt) M + L, which the paper uses in its experiments (the analysis
+uses backward Euler, a = 1).  Local equations (eq. localSolverDD, with the
+forcing F of the step on the right-hand side):
+
+  (a/dt)(phi, w1) - (Phi vel, grad w1) + <Phi vel.n + sqrt(Phi)(phi - phihat), w1> = (F_phi, w1)
+  (a/dt)(Phi u, w2) - (Phi phi, d_x w2) + <Phi phihat n_x, w2> = (f0 Phi v - gamma Phi u + F_u, w2)
+  (a/dt)(Phi v, w3) - (Phi phi, d_y w3) + <Phi phihat n_y, w3> = (-f0 Phi u - gamma Phi v + F_v, w3)
+
+Trace (the formula that follows eq. localSolverDD):
+  phihat^k = {{phi^k}} + sqrt(Phi) {{vel^k . n}}.
+On a wall the exterior state is the mirror state, which gives
+  phihat = phi^- + sqrt(Phi) vel^- . n^-  (zero mass flux through the wall).
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .mesh import BoxMesh, TensorElement
+from .norms import h_norm
+
+
+class SWOperators:
+    def __init__(self, prob, mesh=None, el=None):
+        assert prob.dim == 2
+        self.prob = prob
+        self.mesh = mesh or BoxMesh(prob.n, prob.lo, prob.hi)
+        self.el = el or TensorElement(2, prob.p)
+        mesh, el = self.mesh, self.el
+        ne, npn = mesh.n_el, el.np
+        Phi, f0, gam = prob.Phi, prob.f0, prob.gamma
+        c = prob.a_mass / prob.dt
+        sP = np.sqrt(Phi)
+        J = mesh.jac()
+        Dp = el.grad_phys(mesh)
+        B, W = el.B, el.Wq
+        Mm = np.einsum("q,qi,qj->ij", W * J, B, B)
+        Sx = np.einsum("q,qj,qi->ij", W * J, B, Dp[0])     # (l_j, d_x l_i)
+        Sy = np.einsum("q,qj,qi->ij", W * J, B, Dp[1])
+        Z = np.zeros_like(Mm)
+        # block rows: phi, u, v  (test functions);  block cols: phi, u, v
+        A = np.block([[c * Mm, -Phi * Sx, -Phi * Sy],
+                      [-Phi * Sx, (c + gam) * Phi * Mm, -f0 * Phi * Mm],
+                      [-Phi * Sy, f0 * Phi * Mm, (c + gam) * Phi * Mm]])
+        # face terms with the element's own unknowns: <Phi vel.n + sqrt(Phi) phi, w1>
+        for f in range(4):
+            Bf, Wf, _, _ = el.face_q[f]
+            nv = mesh.normal(f)
+            Mf = np.einsum("q,qi,qj->ij", Wf * mesh.face_jac(f), Bf, Bf)
+            A[:npn, :npn] += sP * Mf
+            A[:npn, npn:2 * npn] += Phi * nv[0] * Mf
+            A[:npn, 2 * npn:] += Phi * nv[1] * Mf
+        self.A = A
+        self.Ainv = np.linalg.inv(A)
+        xq = np.array([el.volume_points(mesh, e) for e in range(ne)])
+        Fq = prob.forcing(xq)                                      # [ne, nq, 3]
+        self.F = np.einsum("q,eqm,qi->emi", W * J, Fq, B).reshape(ne, 3 * npn)
+        self.nbr = np.array([[mesh.neighbour(e, f) for f in range(4)] for e in range(ne)])
+
+    def trace(self, U):
+        """phihat^k at the face quadrature points of every element face: [ne, 4, nfq]."""
+        mesh, el = self.mesh, self.el
+        ne, npn = mesh.n_el, el.np
+        U = U.reshape(ne, 3, npn)
+        sP = np.sqrt(self.prob.Phi)
+        ph = np.zeros((ne, 4, el.nfq))
+        for f in range(4):
+            Bf = el.face_q[f][0]
+            Bo = el.face_q[f ^ 1][0]
+            nv = mesh.normal(f)
+            phm = U[:, 0] @ Bf.T
+            vnm = (U[:, 1] @ Bf.T) * nv[0] + (U[:, 2] @ Bf.T) * nv[1]
+            nb = self.nbr[:, f]
+            inner = nb >= 0
+            Un = U[np.where(inner, nb, 0)]
+            php = Un[:, 0] @ Bo.T
+            vnp = -((Un[:, 1] @ Bo.T) * nv[0] + (Un[:, 2] @ Bo.T) * nv[1])   # vel^+ . n^+
+            interior = 0.5 * (phm + php) + sP * 0.5 * (vnm + vnp)
+            wall = phm + sP * vnm
+            ph[:, f] = np.where(inner[:, None], interior, wall)
+        return ph
+
+    def local_rhs(self, ph):
+        mesh, el = self.mesh, self.el
+        ne, npn = mesh.n_el, el.np
+        Phi, sP = self.prob.Phi, np.sqrt(self.prob.Phi)
+        rhs = self.F.copy().reshape(ne, 3, npn)
+        for f in range(4):
+            Bf, Wf, _, _ = el.face_q[f]
+            nv = mesh.normal(f)
+            t = np.einsum("q,eq,qi->ei", Wf * mesh.face_jac(f), ph[:, f], Bf)
+            rhs[:, 0] += sP * t
+            rhs[:, 1] -= Phi * nv[0] * t
+            rhs[:, 2] -= Phi * nv[1] * t
+        return rhs.reshape(ne, 3 * npn)
+
+    def sweep(self, U):
+        return self.local_rhs(self.trace(U)) @ self.Ainv.T
+
+    def ihdg(self, tol=1e-13, max_iters=100000, u0=None, record=False):
+        U = np.zeros((self.mesh.n_el, 3 * self.el.np)) if u0 is None else u0.copy()
+        hist = []
+        for k in range(1, max_iters + 1):
+            Un = self.sweep(U)
+            inc = h_norm(self.mesh, self.el, Un - U)
+            nrm = h_norm(self.mesh, self.el, Un)
+            U = Un
+            if record:
+                hist.append(inc)
+            if inc <= tol * max(nrm, 1e-300) or not np.isfinite(inc):
+                return U, k, hist
+        return U, max_iters, hist
+
+    def direct_hdg(self):
+        """Solve the HDG system for phihat on interior faces (walls eliminated).
+
+        Conservation: <[[Phi vel.n + sqrt(Phi)(phi - phihat)]], mu>_e = 0.
+        On walls phihat = phi + sqrt(Phi) vel.n is substituted into the local
+        equations.
+        """
+        mesh, el = self.mesh, self.el
+        ne, npn, nfp = mesh.n_el, el.np, el.nfp
+        Phi, sP = self.prob.Phi, np.sqrt(self.prob.Phi)
+        Ab = np.repeat(self.A[None], ne, axis=0)
+        for f in range(4):
+            Bf, Wf, _, _ = el.face_q[f]
+            nv = mesh.normal(f)
+            Mf = np.einsum("q,qi,qj->ij", Wf * mesh.face_jac(f), Bf, Bf)
+            # phihat = phi + sqrt(Phi)(u n_x + v n_y) on the wall
+            Hm = np.hstack([Mf, sP * nv[0] * Mf, sP * nv[1] * Mf])   # <phihat, l_i> as a map of U
+            blk = np.vstack([-sP * Hm, Phi * nv[0] * Hm, Phi * nv[1] * Hm])
+            wall = self.nbr[:, f] < 0
+            Ab[wall] += blk
+        skel = [s for s in mesh.skeleton() if s[2] >= 0]
+        fid = {}
+        for k, (em, fm, ep, fp) in enumerate(skel):
+            fid[(em, fm)] = k
+            fid[(ep, fp)] = k
+        Abinv = np.linalg.inv(Ab)
+        Cf, Df = [], []
+        for f in range(4):
+            Bf, Wf, _, Mu = el.face_q[f]
+            nv = mesh.normal(f)
+            Jf = mesh.face_jac(f)
+            T = np.einsum("q,qb,qi->ib", Wf * Jf, Mu, Bf)          # <mu_b, l_i>
+            Cf.append(np.vstack([sP * T, -Phi * nv[0] * T, -Phi * nv[1] * T]))
+            Tm = T.T                                               # <l_j, mu_c>
+            Df.append(np.hstack([sP * Tm, Phi * nv[0] * Tm, Phi * nv[1] * Tm]))
+        Mface = np.einsum("q,qb,qc->cb", el.face_q[1][1] * mesh.face_jac(1), el.face_q[1][3], el.face_q[1][3])
+        nt = len(skel) * nfp
+        rows, cols, vals = [], [], []
+        rhs = np.zeros(nt)
+
+        def add(r0, c0, blk):
+            rr, cc = np.meshgrid(np.arange(blk.shape[0]) + r0, np.arange(blk.shape[1]) + c0, indexing="ij")
+            rows.append(rr.ravel()); cols.append(cc.ravel()); vals.append(blk.ravel())
+
+        for e in range(ne):
+            faces = [f for f in range(4) if (e, f) in fid]
+            for f in faces:
+                r0 = fid[(e, f)] * nfp
+                DA = Df[f] @ Abinv[e]
+                rhs[r0:r0 + nfp] -= DA @ self.F[e]
+                for f2 in faces:
+                    add(r0, fid[(e, f2)] * nfp, DA @ Cf[f2])
+        for k, (em, fm, ep, fp) in enumerate(skel):
+            Mf = np.einsum("q,qb,qc->cb", el.face_q[fm][1] * mesh.face_jac(fm), el.face_q[fm][3], el.face_q[fm][3])
+            add(k * nfp, k * nfp, -2.0 * sP * Mf)
+        S = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                          shape=(nt, nt)).tocsc()
+        lam = spla.splu(S).solve(rhs)
+        U = np.zeros((ne, 3 * npn))
+        for e in range(ne):
+            r = self.F[e].copy()
+            for f in range(4):
+                if (e, f) in fid:
+                    k = fid[(e, f)]
+                    r += Cf[f] @ lam[k * nfp:(k + 1) * nfp]
+            U[e] = Abinv[e] @ r
+        return U
+
+    def nodal(self, fn):
+        return np.array([fn(self.el.node_points(self.mesh, e)).T.reshape(-1) for e in range(self.mesh.n_el)])

@@ -1,0 +1,69 @@
+"""Pins on the linearised shallow-water oracle (Section 3 and Section 5.2)."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle.norms import h_norm, l2_error
+from oracle.shallow_water import SWOperators
+
+
+def rel(o, a, b):
+    return h_norm(o.mesh, o.el, a - b) / h_norm(o.mesh, o.el, b)
+
+
+@pytest.mark.parametrize("n,p", [((3, 3), 2), ((2, 3), 3)])
+def test_polynomial_reproduction(n, p):
+    """A polynomial (phi, u, v) satisfying the walls is reproduced exactly."""
+    pr = w.sw_poly(n, p, dt=0.01)
+    o = SWOperators(pr)
+    ex = o.nodal(pr.exact)
+    assert np.abs(o.direct_hdg() - ex).max() < 1e-12
+    u, k, _ = o.ihdg(tol=1e-14)
+    assert np.abs(u - ex).max() < 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_ihdg_equals_direct(p):
+    pr = w.sw_standing_wave((6, 6), p, f0=0.37)
+    o = SWOperators(pr)
+    ud = o.direct_hdg()
+    u, k, _ = o.ihdg(tol=1e-13)
+    assert rel(o, u, ud) < 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_h_convergence_order_p_plus_1(p):
+    errs = []
+    for n in [4, 8, 16]:
+        pr = w.sw_standing_wave((n, n), p, f0=0.3)
+        o = SWOperators(pr)
+        ud = o.direct_hdg()
+        errs.append(sum(l2_error(o.mesh, o.el, ud, lambda x, c=c: pr.exact(x)[..., c], field=c) for c in range(3)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > p + 1 - 0.2), rates
+
+
+def test_iterations_independent_of_mesh_at_scaled_dt():
+    """Section 5.2: with dt = h/((p+1)(p+2)) the iteration count does not grow with N."""
+    for p in [1, 3]:
+        ks = []
+        for n in [4, 8, 16]:
+            o = SWOperators(w.sw_standing_wave((n, n), p))
+            _, k, _ = o.ihdg(tol=1e-10)
+            ks.append(k)
+        assert max(ks) <= 1.3 * min(ks), ks
+        assert ks[-1] <= ks[0] + 3
+
+
+def test_conditional_convergence_remark():
+    """Theorem 3 / the remark on dt: a time step far above h/((p+1)(p+2)) breaks the
+    contraction, the scaled one converges."""
+    n, p = 6, 3
+    h = 1.0 / n
+    ok = SWOperators(w.sw_standing_wave((n, n), p, dt=h / ((p + 1) * (p + 2))))
+    _, k, hist = ok.ihdg(tol=1e-10, max_iters=300, record=True)
+    assert k < 300
+    bad = SWOperators(w.sw_standing_wave((n, n), p, dt=40 * h / ((p + 1) * (p + 2))))
+    _, k2, hist2 = bad.ihdg(tol=1e-10, max_iters=300, record=True)
+    assert k2 == 300 or not np.isfinite(hist2[-1])
+    assert hist2[-1] > hist2[len(hist2) // 2]

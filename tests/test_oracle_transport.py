@@ -1,0 +1,201 @@
+"""Pins on the transport oracle (Section 3 and Section 5.1 of the paper).
+
+Each test checks the oracle against something other than itself: exact
+reproduction of polynomial solutions, a dense brute-force solve in a different
+(modal) basis, agreement of three independent solvers (iHDG, the assembled HDG
+trace system, downwind block substitution), the contraction factor of
+Theorem 1, the p+1 convergence order, global conservation, and the iteration
+counts printed in the paper's Table 1.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle.norms import h_norm, l2_error
+from oracle.transport import TransportOperators, brute_force_dense
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "table1_transport_iterations.txt")
+
+
+def rel(o, a, b):
+    return h_norm(o.mesh, o.el, a - b) / h_norm(o.mesh, o.el, b)
+
+
+@pytest.mark.parametrize("n,p,beta", [((3, 2), 2, (1.0, 0.5)), ((2, 3), 3, (-0.4, 0.9)),
+                                      ((2, 2, 2), 2, (0.6, -0.5, 0.3))])
+def test_polynomial_reproduction(n, p, beta):
+    pr = w.transport_poly(n, p, beta, sigma=0.7)
+    o = TransportOperators(pr)
+    ex = o.nodal(pr.exact)
+    assert np.abs(o.direct_hdg() - ex).max() < 1e-12
+    assert np.abs(o.downwind() - ex).max() < 1e-12
+    u, k, _ = o.ihdg(tol=1e-14)
+    assert np.abs(u - ex).max() < 1e-11
+
+
+@pytest.mark.parametrize("n,p,beta", [((2, 1), 1, (1.0, 0.5)), ((2, 2), 2, (0.7, -0.4)),
+                                      ((2, 1, 1), 1, (0.5, 0.3, -0.8))])
+def test_brute_force_modal_dense(n, p, beta):
+    """Dense volume+trace solve in a Legendre basis with a (p+4)-point rule."""
+    pr = w.transport_poly(n, p, beta, sigma=0.7, deg=p + 1)
+    o = TransportOperators(pr)
+    ud = o.direct_hdg()
+    uh = brute_force_dense(pr)
+    rn = np.array([[o.el.r1[im[a]] for a in range(pr.dim)] for im in o.el.node_multi])
+    ub = np.array([[uh(e, r) for r in rn] for e in range(o.mesh.n_el)])
+    assert np.abs(ub - ud).max() < 1e-12
+    u, _, _ = o.ihdg(tol=1e-14)
+    assert np.abs(u - ud).max() < 1e-11
+
+
+@pytest.mark.parametrize("make", [lambda: w.config1(), lambda: w.config2(n=8),
+                                  lambda: w.transport_affine_beta((6, 5), 3),
+                                  lambda: w.config3(n=3, p=2)])
+def test_ihdg_equals_direct_equals_downwind(make):
+    pr = make()
+    o = TransportOperators(pr)
+    ud = o.direct_hdg()
+    assert rel(o, o.downwind(), ud) < 1e-12
+    u, k, _ = o.ihdg(tol=1e-13)
+    assert rel(o, u, ud) < 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_contraction_factor_theorem1(p):
+    """Spectral radius of the iteration <= 2^{-1/2} (Theorem 1); exactly 1/2 when
+    the flow is axis aligned or p = 1 (the remark after Theorem 1)."""
+    for beta in [(1.0, 0.5), (0.3, 1.0), (1.0, 1.0)]:
+        o = TransportOperators(w.transport_const((3, 3), p, beta, sigma=0.0))
+        rho = max(np.abs(np.linalg.eigvals(t)).max() for t in o.iteration_matrix_diag_blocks())
+        assert 0.5 - 1e-7 <= rho <= 2 ** -0.5
+        if p == 1:
+            assert abs(rho - 0.5) < 1e-7   # defective blocks: eigenvalues good to ~sqrt(eps)
+    o = TransportOperators(w.transport_const((3, 3), p, (1.0, 0.0), sigma=0.0))
+    rho = max(np.abs(np.linalg.eigvals(t)).max() for t in o.iteration_matrix_diag_blocks())
+    assert abs(rho - 0.5) < 1e-7
+
+
+def test_contraction_observed_matches_theorem1():
+    """Theorem 1: increments decay like c(k)/2^k with c a polynomial of degree J
+    (J = number of flow layers), so successive ratios fall monotonically towards 1/2."""
+    o = TransportOperators(w.transport_const((4, 4), 2, (1.0, 0.0), sigma=0.0))
+    u, k, hist = o.ihdg(tol=1e-13, record=True, u0=np.random.default_rng(1).standard_normal((16, 9)))
+    r = np.array(hist[1:]) / np.array(hist[:-1])
+    tail = r[4:40]
+    assert np.all(np.diff(tail) < 0)
+    assert np.all(tail > 0.5) and tail[-1] < 0.56
+    # bound c(k)/2^k with deg c <= J = 4:  hist[k] * 2^k / (k+1)^4 stays bounded
+    kk = np.arange(1, len(hist) + 1)
+    s = np.array(hist) * 2.0 ** kk / (kk + 1) ** 4
+    assert s[-1] <= s[:10].max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_h_convergence_order_p_plus_1(p):
+    errs = []
+    for n in [4, 8, 16]:
+        pr = w.transport_const((n, n), p, (1.0, 0.5), sigma=1.0)
+        o = TransportOperators(pr)
+        errs.append(l2_error(o.mesh, o.el, o.downwind(), lambda x: pr.exact(x)[..., 0]))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > p + 1 - 0.2), rates
+
+
+def test_global_conservation():
+    """sum_K (sigma u, 1) + int_out beta.n u - int_in |beta.n| g = int f (div beta = 0)."""
+    from oracle.reference_element import gauss, lagrange
+    pr = w.config2(n=6, p=3)
+    o = TransportOperators(pr)
+    u, _, _ = o.ihdg(tol=1e-14)
+    # integrate with an independent (p+4)-point rule
+    xg, wg = gauss(pr.p + 4)
+    L, _ = lagrange(o.el.r1, xg)
+    sig = pr.sigma_of_elements()
+    lhs, rhs = 0.0, 0.0
+    h = o.mesh.h
+    for e in range(o.mesh.n_el):
+        U = u[e].reshape(pr.p + 1, pr.p + 1)            # [iy, ix]
+        x0 = o.mesh.el_origin(e)
+        X, Y = np.meshgrid(x0[0] + h[0] / 2 * (xg + 1), x0[1] + h[1] / 2 * (xg + 1), indexing="xy")
+        uq = L @ U @ L.T                                   # [qy, qx]
+        Wq = np.outer(wg, wg) * h[0] * h[1] / 4
+        pts = np.stack([X, Y], -1)
+        lhs += sig[e] * np.sum(Wq * uq)
+        rhs += np.sum(Wq * pr.forcing(pts, sig[e])[..., 0])
+        for f in range(4):
+            if o.mesh.neighbour(e, f) >= 0:
+                continue
+            a, s = divmod(f, 2)
+            t = 1 - a
+            end = L[:, :0]  # unused
+            rt = xg
+            xb = x0.copy()
+            xb[a] += h[a] if s else 0.0
+            pts = np.tile(xb, (len(xg), 1))
+            pts[:, t] = x0[t] + h[t] / 2 * (rt + 1)
+            # trace of u on the face: evaluate the tensor interpolant at r_a = +-1
+            la, _ = lagrange(o.el.r1, np.array([1.0 if s else -1.0]))
+            Lt, _ = lagrange(o.el.r1, rt)
+            tr = (Lt @ U @ la[0]) if a == 0 else (la[0] @ U @ Lt.T)
+            nv = np.zeros(2); nv[a] = 1.0 if s else -1.0
+            bn = pr.beta_at(pts) @ nv
+            wf = wg * h[t] / 2
+            g = pr.bdry(pts)[..., 0]
+            lhs += np.sum(wf * np.where(bn >= 0, bn * tr, 0.0))
+            lhs -= np.sum(wf * np.where(bn < 0, -bn * g, 0.0))
+    assert abs(lhs - rhs) < 1e-6 * abs(rhs) + 1e-12
+
+
+def _gold():
+    rows = []
+    for line in open(GOLD):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append(tuple(int(v) for v in line.split()))
+    return rows
+
+
+@pytest.mark.parametrize("row", [r for r in _gold() if r[0] == 2 and r[1] <= 256])
+def test_paper_table1_2d_iteration_counts(row):
+    """The 2-D discontinuous experiment: counts within one iteration of Table 1."""
+    dim, n_el, p, iters = row
+    n = int(round(np.sqrt(n_el)))
+    o = TransportOperators(w.transport_e1(n, p))
+    M = np.einsum("q,qi,qj->ij", o.el.Wq * o.mesh.jac(), o.el.B, o.el.B)
+    u = np.zeros((o.mesh.n_el, o.el.np))
+    for k in range(1, 2000):
+        un = o.sweep(u)
+        d = un - u
+        u = un
+        if np.sqrt(np.einsum("ei,ij,ej->", d, M, d)) < 1e-10:
+            break
+    assert abs(k - iters) <= 1, (k, iters)
+
+
+@pytest.mark.parametrize("row", [r for r in _gold() if r[0] == 3 and r[1] <= 64 and r[2] == 3])
+def test_paper_table1_3d_iteration_counts(row):
+    """The 3-D smooth experiment (stopping on the change of the exact error): within 10%."""
+    dim, n_el, p, iters = row
+    n = int(round(n_el ** (1 / 3)))
+    pr = w.transport_e2(n, p)
+    o = TransportOperators(pr)
+    u = np.zeros((o.mesh.n_el, o.el.np))
+    prev = None
+    for k in range(1, 2000):
+        u = o.sweep(u)
+        e = l2_error(o.mesh, o.el, u, lambda x: pr.exact(x)[..., 0])
+        if prev is not None and abs(e - prev) < 1e-10:
+            break
+        prev = e
+    assert abs(k - iters) <= 0.1 * iters + 1, (k, iters)
+
+
+def test_iteration_count_independent_of_p():
+    """Section 5.1: the number of iterations barely depends on the order."""
+    ks = {}
+    for p in [2, 4]:
+        o = TransportOperators(w.transport_const((12, 12), p, (1.0, 0.5), sigma=1.0))
+        _, ks[p], _ = o.ihdg(tol=1e-12)
+    assert abs(ks[2] - ks[4]) <= 0.1 * ks[2]
