@@ -1,0 +1,208 @@
+"""Benchmark of the iHDG sweep on one MI355X.
+
+Workload: 2-D steady transport on the unit square, 256 x 256 quads, p = 4
+(25 DOF per element), divergence-free variable beta = (1 + 0.5 sin(2 pi a y),
+1 + 0.5 cos(2 pi b x)) with a, b ~ U[0.5, 2] drawn from seed 0, reaction
+sigma_K ~ U[0.1, 1] per element, manufactured u = sin(pi x) sin(pi y).  Every
+element has its own pre-factored local operator, so the sweep streams the
+per-element operators from HBM.
+
+A step is one iHDG sweep (gather, face step, local solve, trace update and
+increment norm) over all 65 536 elements, on the FP64 path.  `value` is
+element-DOF updates per second.  The same line also reports the mixed path
+(FP32 operators) sweep rate, time-to-tolerance for both, the error of each
+result against the CPU oracle, the roofline of the sweep kernel and the
+oracle's own throughput on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-oracle]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle error and CPU baseline legs")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="a short run for hardware counters: a few sweeps plus one copy of known size")
+    return ap.parse_args()
+
+
+def algorithmic_bytes_per_element(n_loc, n_in, nf, fp):
+    """Bytes one sweep must move per element: the operator G_K, the affine part
+    c_K, the previous and the new iterate, and the face map."""
+    return n_loc * n_in * fp + 3 * n_loc * fp + nf * 4
+
+
+def time_sweeps(torch, s, k):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.sweep(k)
+    e1.record(s.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3  # seconds
+
+
+def time_fp32_sweeps(torch, s, k):
+    """Time k FP32 correction sweeps through a mixed solve's inner path."""
+    return None
+
+
+def cpu_baseline(pr_full):
+    """The oracle's iHDG sweep timed on the host on a bounded sample: the same
+    workload recipe on a 96 x 96 sub-mesh (same seed, same beta, fresh sigma
+    draw of that size), 10 sweeps after its setup."""
+    import workloads as w
+    from oracle.transport import TransportOperators
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    n = 96
+    pr = w.config2(n=n, p=pr_full.p)
+    o = TransportOperators(pr)
+    u = np.zeros((o.mesh.n_el, o.el.np))
+    u = o.sweep(u)
+    k = 10
+    t0 = time.perf_counter()
+    for _ in range(k):
+        u = o.sweep(u)
+    dt = time.perf_counter() - t0
+    dofs = o.mesh.n_el * o.el.np * k
+    return {"value": dofs / dt, "unit": "element-DOF updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"oracle NumPy sweep, same recipe on {n}x{n} quads p={pr.p}, {k} sweeps after setup"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
+                                   "(see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import workloads as w
+    from paper_1605_03228_amd.problem_io import make_solver
+
+    dev = "cuda"
+    pr = w.config2(seed=0, n=args.n, p=args.p)
+    t0 = time.perf_counter()
+    s64 = make_solver(pr, device=dev, block_waves=args.waves)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    sz = s64.sz
+    n_el, n_loc, n_in = sz["n_el"], sz["n_loc"], sz["n_in"]
+    nf = 4
+
+    if args.profile_pass:
+        s64.sweep(10)
+        torch.cuda.synchronize()
+        nbytes = 1 << 29
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_pass": True, "copy_bytes": nbytes, "sweeps": 10}))
+        return
+
+    # ---- FP64 sweep throughput ------------------------------------------------
+    s64.sweep(args.warmup)
+    torch.cuda.synchronize()
+    t = time_sweeps(torch, s64, args.steps)
+    ms_per_step = t / args.steps * 1e3
+    value = n_el * n_loc * args.steps / t
+    bpe64 = algorithmic_bytes_per_element(n_loc, n_in, nf, 8)
+    achieved = bpe64 * n_el / (t / args.steps) / 1e9
+
+    # ---- time to tolerance, FP64 ------------------------------------------------
+    s64b = make_solver(pr, device=dev, block_waves=args.waves)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r64 = s64b.solve(1e-12)
+    torch.cuda.synchronize()
+    ttt64 = time.perf_counter() - t0
+    u64 = s64b.get_solution()
+
+    # ---- mixed precision ---------------------------------------------------------
+    t0 = time.perf_counter()
+    smx = make_solver(pr, device=dev, prec=1, block_waves=args.waves)
+    torch.cuda.synchronize()
+    setup_mx = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rmx = smx.solve(1e-10)
+    torch.cuda.synchronize()
+    tttmx = time.perf_counter() - t0
+    umx = smx.get_solution()
+    fp32_rate = None
+    if rmx["fp32_sweeps"] > 0:
+        # FP32 sweep rate from the solve itself: total time minus the FP64 sweeps at their measured rate
+        t32 = tttmx - rmx["fp64_sweeps"] * (t / args.steps)
+        if t32 > 0:
+            fp32_rate = n_el * n_loc * rmx["fp32_sweeps"] / t32
+
+    err64 = errmx = None
+    cpu = None
+    if not args.no_oracle:
+        from oracle.norms import h_norm
+        from oracle.transport import TransportOperators
+        o = TransportOperators(pr)
+        ref = o.downwind()
+        a64 = u64.reshape(n_el, -1).cpu().numpy()
+        amx = umx.reshape(n_el, -1).cpu().numpy()
+        nr = h_norm(o.mesh, o.el, ref)
+        err64 = h_norm(o.mesh, o.el, a64 - ref) / nr
+        errmx = h_norm(o.mesh, o.el, amx - ref) / nr
+        cpu = cpu_baseline(pr)
+
+    line = {
+        "metric": "iHDG element-DOF updates/s/sweep (FP64 vs mixed) + p50/p99 solve latency",
+        "value": value,
+        "unit": "element-DOF updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded analytic coefficients, manufactured solution)",
+        "config": {"workload": f"2-D steady transport {args.n}x{args.n} quads p={args.p}, variable beta, "
+                               f"per-element sigma, per-element local operators (FP64)",
+                   "n_el": n_el, "n_loc": n_loc, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_element": bpe64, "kernel": "k_sweep<double, transport, 2, p, per-element>"},
+        "fp64": {"setup_s": setup_s, "solve_tol": 1e-12, "time_to_tol_s": ttt64, "sweeps": r64["iters"],
+                 "status": r64["status"], "rel_err_vs_oracle": err64},
+        "mixed": {"setup_s": setup_mx, "solve_tol": 1e-10, "time_to_tol_s": tttmx,
+                  "fp64_sweeps": rmx["fp64_sweeps"], "fp32_sweeps": rmx["fp32_sweeps"],
+                  "outer_steps": rmx["outer_steps"], "status": rmx["status"],
+                  "fp32_sweep_rate": fp32_rate, "rel_err_vs_oracle": errmx,
+                  "speedup_time_to_tol_vs_fp64": (ttt64 / tttmx) if tttmx > 0 else None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,250 @@
+/*
+ * ihdg.h -- C ABI of the MI355X iHDG library.
+ *
+ * The library solves the upwind-HDG discretisation of a linear first-order
+ * system (the paper's Section 2, eq. LPDE, discretised as in eqs. HDGlocal,
+ * HDGeqn and RiemannFluxBoth) with the iterative HDG method (Algorithm 1):
+ * every sweep solves each element's local problem independently, taking the
+ * weighted trace of the previous iterate on its faces, so no global trace
+ * system is ever formed.  Three PDE families are supported, as in the paper:
+ *
+ *   IHDG_TRANSPORT      div(beta u) + sigma u = f, u = g on the inflow
+ *                       boundary (Section 3, eqs. transportLocalk1 and
+ *                       transportLocale; sigma is an added reaction);
+ *   IHDG_SHALLOW_WATER  one implicit step of the linearised shallow-water
+ *                       system (Section 3, eq. linearizedShallow and the local
+ *                       equations localSolverDD), walls on the boundary;
+ *   IHDG_CONVDIFF       first-order convection-diffusion (Section 4,
+ *                       eq. Convection-diffusion-eqn and the iterative scheme
+ *                       that follows it), Dirichlet data on the boundary.
+ *
+ * Discretisation: uniform box of quads (dim 2) or hexes (dim 3); tensor Q^p
+ * Lagrange basis on Gauss-Lobatto-Legendre nodes; Gauss-Legendre quadrature
+ * with p+2 points per direction on volumes and faces.
+ *
+ * Memory ownership.  Every device buffer (coefficients, workspace, scratch,
+ * solution copies) is allocated by the caller; the library never calls
+ * hipMalloc or hipFree.  The library owns only the host-side context.
+ * `workspace` must stay allocated until ihdg_destroy; `scratch` may be freed
+ * as soon as ihdg_setup has returned.  Coefficient arrays are read during
+ * ihdg_setup only.
+ *
+ * Streams.  All device work of a context is ordered on the stream given to
+ * ihdg_setup (or ihdg_set_stream).  Calls that return host values
+ * synchronise that stream; the others only enqueue work.
+ *
+ * Errors.  Every call returns an ihdg_status; no exception crosses the ABI.
+ * On error, output arguments are left untouched and ihdg_last_error() gives a
+ * message.  Asynchronous HIP faults surface as IHDG_ERR_HIP at the next
+ * synchronising call.  IHDG_ERR_DIVERGED and IHDG_ERR_MAXITER leave the last
+ * iterate in place (readable with ihdg_get_solution).
+ *
+ * Thread safety.  A context may be used by one host thread at a time;
+ * distinct contexts are independent.
+ */
+#ifndef IHDG_H
+#define IHDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihdg_ctx ihdg_ctx;
+
+typedef enum {
+  IHDG_OK = 0,
+  IHDG_ERR_ARG = 1,            /* invalid argument (null pointer, bad size, bad enum)     */
+  IHDG_ERR_UNSUPPORTED = 2,    /* valid but not supported (order, dim, mixed-sign face)   */
+  IHDG_ERR_NOMEM = 3,          /* workspace or scratch smaller than ihdg_footprint says   */
+  IHDG_ERR_HIP = 4,            /* a HIP runtime call or kernel failed                     */
+  IHDG_ERR_SINGULAR_LOCAL = 5, /* a local HDG matrix could not be factored                */
+  IHDG_ERR_DIVERGED = 6,       /* increment non-finite or grew 1e3x above its minimum    */
+  IHDG_ERR_MAXITER = 7         /* tolerance not reached within max_iters sweeps           */
+} ihdg_status;
+
+typedef enum { IHDG_TRANSPORT = 0, IHDG_SHALLOW_WATER = 1, IHDG_CONVDIFF = 2 } ihdg_pde;
+
+typedef enum {
+  IHDG_FP64 = 0,  /* FP64 operators, FP64 state, FP64 sweeps                               */
+  IHDG_MIXED = 1  /* FP32 operators and FP32 correction sweeps; FP64 defect sweeps, FP64
+                     convergence test and FP64 solution update (defect correction)          */
+} ihdg_precision;
+
+/* Uniform box [lo, hi] split into n[0] x n[1] (x n[2]) elements.  Elements are
+ * numbered lexicographically, x fastest.  Unused entries (dim 2: index 2) are
+ * ignored. */
+typedef struct {
+  int32_t dim;     /* 2 or 3 (3 only for IHDG_TRANSPORT) */
+  int32_t n[3];
+  double lo[3];
+  double hi[3];
+} ihdg_mesh;
+
+/* Sizes of the discretisation (filled by ihdg_sizes). */
+typedef struct {
+  int64_t n_el;      /* number of elements                                              */
+  int64_t n_face;    /* number of unique faces of the skeleton                          */
+  int32_t np;        /* nodes per element and field, (p+1)^dim                           */
+  int32_t m;         /* fields: 1 transport, 3 shallow water, dim+1 convection-diffusion */
+  int32_t n_loc;     /* local unknowns, m*np                                             */
+  int32_t nq;        /* volume quadrature points per element, (p+2)^dim                  */
+  int32_t nfq;       /* quadrature points per face, (p+2)^(dim-1)                        */
+  int32_t nfp;       /* nodes per face, (p+1)^(dim-1)                                    */
+  int32_t n_in;      /* face values feeding a local solve, 2*dim*nfp                     */
+  int32_t m_f;       /* components of the forcing array: 1, or 3 for shallow water       */
+} ihdg_sizes_t;
+
+/*
+ * Coefficients and data, all device pointers to FP64 arrays, all read only
+ * during ihdg_setup.  Quadrature points are the ones ihdg_quadrature_points
+ * returns.  Faces are numbered as ihdg_quadrature_points documents; every
+ * face-point array is indexed by unique face, so both elements of a face see
+ * the same values.
+ *
+ *   beta_q    [n_el][nq][dim]  advection field (transport, conv.-diff.), or NULL
+ *                              to use beta_const everywhere
+ *   divbeta_q [n_el][nq]       div beta at the volume points, or NULL for 0
+ *   bn_fq     [n_face][nfq]    beta . e_axis at the face points (e_axis = the
+ *                              face's coordinate axis, pointing to +axis), or
+ *                              NULL to take it from beta_const
+ *   sigma_el  [n_el]           transport reaction per element, or NULL for
+ *                              sigma_const
+ *   f_q       [n_el][nq][m_f]  forcing at the volume points, or NULL for 0
+ *   g_fq      [n_face][nfq]    boundary data at the face points (transport:
+ *                              inflow values; conv.-diff.: Dirichlet values),
+ *                              entries of interior faces are ignored; NULL = 0
+ *
+ * The shared-operator path (one reference local operator for all elements)
+ * is taken when the local matrices cannot differ between elements: transport
+ * with beta_q, divbeta_q, bn_fq and sigma_el all NULL; shallow water always;
+ * conv.-diff. with beta_q and bn_fq NULL.  Otherwise every element gets its
+ * own pre-factored operator.
+ */
+typedef struct {
+  const double* beta_q;
+  const double* divbeta_q;
+  const double* bn_fq;
+  const double* sigma_el;
+  const double* f_q;
+  const double* g_fq;
+  double beta_const[3];
+  double sigma_const;
+  double kappa;      /* conv.-diff.: diffusion coefficient (kappa > 0)                 */
+  double nu;         /* conv.-diff.: reaction nu                                       */
+  double Phi;        /* shallow water: mean geopotential Phi > 0                       */
+  double f0;         /* shallow water: Coriolis parameter (constant)                   */
+  double gamma;      /* shallow water: bottom friction                                 */
+  double mass_coef;  /* shallow water: coefficient a/dt of the mass term (a = 2: CN)   */
+} ihdg_coeffs;
+
+typedef struct {
+  ihdg_precision prec;
+  int32_t check_every;     /* sweeps per convergence check (even; 0 = library default)        */
+  int32_t max_iters;       /* sweep cap of ihdg_solve (0 = 100000)                            */
+  int32_t krylov_restart;  /* 0: plain iHDG; m > 0: GMRES(m) on (I - T)u = c, T the sweep     */
+  double inner_rtol;       /* mixed: inner FP32 loop stops when its increment <= this x the
+                              correction (0 = 1e-6)                                           */
+  int32_t use_graph;       /* 1: replay sweep batches from a captured HIP graph               */
+  int32_t force_per_element; /* 1: per-element operators even where one could be shared      */
+  int32_t block_waves;     /* waves per workgroup of the sweep kernel (0 = autotuned/default)  */
+} ihdg_options;
+
+/* Discretisation sizes for (mesh, order, pde).  No device work. */
+ihdg_status ihdg_sizes(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, ihdg_sizes_t* out);
+
+/*
+ * Quadrature points at which the caller evaluates its coefficients.
+ *   xq_dev  [n_el][nq][dim]   volume points of every element (may be NULL)
+ *   xfq_dev [n_face][nfq][dim] face points of every unique face (may be NULL)
+ * Unique faces: first all faces normal to x, then normal to y, then z.  The
+ * faces normal to axis a are indexed lexicographically (x fastest) by their
+ * integer position j with j_a in [0, n_a] and j_b in [0, n_b) for b != a.
+ * Points inside a volume or face are ordered lexicographically over the
+ * Gauss points, lowest remaining axis fastest.  `stream` is a hipStream_t.
+ */
+ihdg_status ihdg_quadrature_points(const ihdg_mesh* mesh, int32_t order, double* xq_dev,
+                                   double* xfq_dev, void* stream);
+
+/*
+ * Device memory the caller must provide to ihdg_setup for these arguments:
+ * `persistent_bytes` for the workspace (operators, state, maps) and
+ * `scratch_bytes` for setup-only scratch.  `coeffs` decides shared versus
+ * per-element operators (it may be NULL: per-element unless shallow water).
+ */
+ihdg_status ihdg_footprint(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde,
+                           const ihdg_coeffs* coeffs, const ihdg_options* opts,
+                           size_t* persistent_bytes, size_t* scratch_bytes);
+
+/*
+ * Assemble every local HDG operator, factor it (LU with partial pivoting, FP64,
+ * on the GPU), and store G_K = L_K^{-1} E_K and c_K = L_K^{-1} F_K, so that a
+ * sweep is u_K^{k+1} = c_K + G_K x_K(u^k) (the local solve of eq. iHDGlocal
+ * with the weighted trace of eq. iHDGtrace as its input x_K).  The initial
+ * iterate is u^0 = 0.  `workspace` and `scratch` are device buffers of at
+ * least the ihdg_footprint sizes, 256-byte aligned.  `stream` is a
+ * hipStream_t.  Synchronises the stream (it checks for setup errors).
+ * Returns IHDG_ERR_UNSUPPORTED for an interior transport face on which beta.n
+ * changes sign.
+ */
+ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
+                       const ihdg_options* opts, void* workspace, size_t workspace_bytes,
+                       void* scratch, size_t scratch_bytes, void* stream, ihdg_ctx** out);
+
+/*
+ * Run n_sweeps iHDG sweeps (Algorithm 1, the local solve and trace update) in
+ * the context's working precision: FP64 for IHDG_FP64; for IHDG_MIXED the
+ * sweeps are FP64 too (ihdg_solve is where the mixed path runs).  If
+ * incr_norm is not NULL it receives, after synchronising, the h-norm of the
+ * last increment ||u^k - u^{k-1}||_h and, in incr_norm[1], ||u^k||_h.
+ * The h-norm is ||e||_h^2 = sum_K |J_K| sum_i W_i e_i^2 (GLL weights W_i).
+ */
+ihdg_status ihdg_sweep(ihdg_ctx* ctx, int32_t n_sweeps, double* incr_norm);
+
+/*
+ * Iterate from the current iterate until ||u^k - u^{k-1}||_h <= tol ||u^k||_h
+ * (IHDG_FP64, plain iHDG), or until the FP64 defect ||psi(u) - u||_h <= tol
+ * ||u||_h (IHDG_MIXED; and the Krylov path, on its residual).  iters receives
+ * the number of sweeps (FP64 + FP32 for mixed), final_incr the last relative
+ * increment, final_defect the relative FP64 defect of the returned iterate
+ * (one extra FP64 sweep, not counted in iters).  Any output may be NULL.
+ */
+ihdg_status ihdg_solve(ihdg_ctx* ctx, double tol, int32_t* iters, double* final_incr,
+                       double* final_defect);
+
+/* Relative FP64 defect ||psi(u) - u||_h / ||u||_h of the current iterate, where
+ * psi is one FP64 sweep; defect_norm[0] = relative, defect_norm[1] = absolute.
+ * Does not change the iterate. */
+ihdg_status ihdg_residual(ihdg_ctx* ctx, double* defect_norm);
+
+/* Copy the current iterate to / from u_dev, FP64 [n_el][m][np] (element-major,
+ * fields contiguous per element, GLL nodes lexicographic, x fastest).
+ * Stream-ordered; no synchronisation. */
+ihdg_status ihdg_get_solution(ihdg_ctx* ctx, double* u_dev);
+ihdg_status ihdg_set_solution(ihdg_ctx* ctx, const double* u_dev);
+
+/* Change the stream all later work of ctx is ordered on (a hipStream_t). */
+ihdg_status ihdg_set_stream(ihdg_ctx* ctx, void* stream);
+
+/* Statistics of the last ihdg_solve: number of FP64 and FP32 sweeps, outer
+ * defect-correction steps, Krylov iterations. */
+typedef struct {
+  int64_t fp64_sweeps;
+  int64_t fp32_sweeps;
+  int32_t outer_steps;
+  int32_t krylov_iters;
+  int32_t shared_operator;  /* 1 if one operator is shared by all elements */
+  int32_t kernel_waves;     /* waves per workgroup used by the sweep kernel */
+} ihdg_stats;
+ihdg_status ihdg_get_stats(const ihdg_ctx* ctx, ihdg_stats* out);
+
+const char* ihdg_last_error(const ihdg_ctx* ctx);
+const char* ihdg_status_string(ihdg_status s);
+void ihdg_destroy(ihdg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IHDG_H */

@@ -1,0 +1,85 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ihdg.h"
+#include "common.hpp"
+
+namespace ihdg {
+
+RefTab make_reftab(int p, int dim);
+
+// Coefficient pointers as the setup kernels see them (see ihdg_coeffs).
+struct Coeffs {
+  const double* beta_q;
+  const double* divbeta_q;
+  const double* bn_fq;
+  const double* sigma_el;
+  const double* f_q;
+  const double* g_fq;
+  double beta_const[3];
+  double sigma_const, kappa, nu, Phi, f0, gamma, mass_coef;
+};
+
+struct SetupArgs {
+  MeshInfo mi;
+  RefTab rt;
+  Coeffs cf;
+  int pde, m, n_loc, n_in, m_f;
+  int shared_rep;   // 1: assemble one representative element, all faces treated as interior
+  int64_t e0;       // first element of this chunk
+  int64_t count;    // elements in this chunk
+  double* scratch;  // count x n_loc x ncol augmented matrices
+  int ncol;
+  double* G64;      // per element: [blk][n_loc][n_in][64]; shared: [n_loc][n_in]
+  float* G32;
+  double* c64;      // [blk][n_loc][64]
+  double* Linv;     // shared: [n_loc][n_loc]
+  double* P64;      // conv.-diff. face projections, per element: [blk][nf][3 nfp nfp][64]; shared: [nf][3 nfp nfp]
+  float* P32;
+  int* flags;       // [0] singular local matrix, [1] interior face with mixed-sign beta.n
+};
+
+// Sweep kernel arguments (type-erased; T = double or float).
+struct SweepArgs {
+  const void* uin;
+  void* uout;
+  const void* c;
+  const void* G;
+  const void* P;
+  const int* fmap;
+  const double* wnorm;  // [n_loc] |J| x GLL weight of each local unknown
+  double* partials;     // [n_blk][2]: sum w (uout-uin)^2, sum w uout^2
+  int64_t n_blk;
+  double sqrt_phi;      // shallow water sqrt(Phi)
+};
+
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+hipError_t launch_shared_c(const SetupArgs& a, hipStream_t s);
+hipError_t launch_maps(const SetupArgs& a, int* fmap, hipStream_t s);
+hipError_t launch_quad_points(const MeshInfo& mi, const RefTab& rt, double* xq, double* xfq, hipStream_t s);
+
+// Sweep dispatch: returns hipErrorInvalidValue if (pde, dim, p) has no instance.
+hipError_t launch_sweep(int pde, int dim, int p, bool fp32, bool shared, int waves, const SweepArgs& a,
+                        hipStream_t s);
+hipError_t launch_sweep_transport(int dim, int p, bool fp32, bool shared, int waves, const SweepArgs& a,
+                                  hipStream_t s);
+hipError_t launch_sweep_sw(int p, bool fp32, bool shared, int waves, const SweepArgs& a, hipStream_t s);
+hipError_t launch_sweep_cd(int p, bool fp32, bool shared, int waves, const SweepArgs& a, hipStream_t s);
+
+// Small vector kernels (vector_ops.hip).
+hipError_t launch_reduce_partials(const double* partials, int64_t n_blk, double* out2, hipStream_t s);
+hipError_t launch_diff_to_f32(const double* a, const double* b, float* out, int64_t n, hipStream_t s);
+hipError_t launch_add_f32_to_f64(double* u, const float* d, int64_t n, hipStream_t s);
+hipError_t launch_fill_zero_f32(float* x, int64_t n, hipStream_t s);
+hipError_t launch_fill_zero_f64(double* x, int64_t n, hipStream_t s);
+hipError_t launch_to_user(const double* u_il, double* u_user, int64_t n_el, int n_loc, hipStream_t s);
+hipError_t launch_from_user(const double* u_user, double* u_il, int64_t n_el, int n_loc, hipStream_t s);
+hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s);
+hipError_t launch_dots(const double* x, const double* const* ys, int k, const double* w, int n_loc,
+                       int64_t n_blk, double* partial, double* out, hipStream_t s);
+
+}  // namespace ihdg

@@ -1,0 +1,599 @@
+// Setup kernels (FP64, run once per problem):
+//   * quadrature-point coordinates for the caller,
+//   * the per-(element, face) source map of the gather,
+//   * assembly of each element's local HDG system  L_K u = F_K + E_K x, where
+//     x holds the face-node values the sweep feeds in (one block of nfp values
+//     per local face), for the three PDEs,
+//   * Gauss-Jordan elimination with partial pivoting, which yields
+//     G_K = L_K^{-1} E_K and c_K = L_K^{-1} F_K (or, for a shared operator,
+//     G = L^{-1} E and L^{-1} itself, applied to every element's F_K after).
+//
+// One workgroup handles one element; the augmented matrix lives in global
+// scratch (at most 147 x 176 doubles per element).
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace ihdg {
+
+constexpr int kMaxNq = 216;   // (p+2)^3 for p = 4
+constexpr int kMaxNfq = 36;   // (p+2)^2 for p = 4
+constexpr int kMaxNloc = 147; // 3 x 7^2
+constexpr int kMaxNf = 6;
+constexpr int kST = 256;      // threads per setup workgroup
+
+// ---------------------------------------------------------------------------
+// reference basis evaluated from the 1-D tables (tensor products)
+// ---------------------------------------------------------------------------
+struct Basis {
+  const RefTab& t;
+  const MeshInfo& m;
+  __device__ Basis(const RefTab& t_, const MeshInfo& m_) : t(t_), m(m_) {}
+  __device__ void split(int k, int base, int* idx) const {
+    idx[0] = k % base;
+    idx[1] = (k / base) % base;
+    idx[2] = k / (base * base);
+  }
+  __device__ double W(int q) const {  // volume weight times |J|
+    int qa[3];
+    split(q, t.nq1, qa);
+    double w = m.jac;
+    for (int a = 0; a < m.dim; ++a) w *= t.wq[qa[a]];
+    return w;
+  }
+  __device__ double B(int q, int i) const {
+    int qa[3], ia[3];
+    split(q, t.nq1, qa);
+    split(i, t.n1, ia);
+    double v = 1.0;
+    for (int a = 0; a < m.dim; ++a) v *= t.L[qa[a]][ia[a]];
+    return v;
+  }
+  // physical derivative d/dx_a of basis i at volume point q
+  __device__ double D(int a, int q, int i) const {
+    int qa[3], ia[3];
+    split(q, t.nq1, qa);
+    split(i, t.n1, ia);
+    double v = 2.0 / m.h[a];
+    for (int b = 0; b < m.dim; ++b) v *= (b == a) ? t.dL[qa[b]][ia[b]] : t.L[qa[b]][ia[b]];
+    return v;
+  }
+  // face point qf of local face f: weight times face Jacobian
+  __device__ double Wf(int f, int qf) const {
+    int ax = f >> 1;
+    double w = m.fjac[ax];
+    int r = qf;
+    for (int b = 0; b < m.dim; ++b) {
+      if (b == ax) continue;
+      w *= t.wq[r % t.nq1];
+      r /= t.nq1;
+    }
+    return w;
+  }
+  // volume basis i at face point qf of local face f
+  __device__ double Bf(int f, int qf, int i) const {
+    int ax = f >> 1, s = f & 1;
+    int ia[3];
+    split(i, t.n1, ia);
+    double v = t.Lend[s][ia[ax]];
+    int r = qf;
+    for (int b = 0; b < m.dim; ++b) {
+      if (b == ax) continue;
+      v *= t.L[r % t.nq1][ia[b]];
+      r /= t.nq1;
+    }
+    return v;
+  }
+  // true when volume node i lies on local face f
+  __device__ bool on_face(int f, int i) const {
+    int ax = f >> 1, s = f & 1;
+    int ia[3];
+    split(i, t.n1, ia);
+    return ia[ax] == (s ? t.n1 - 1 : 0);
+  }
+};
+
+struct ElemData {
+  double beta[kMaxNq][3];
+  double divb[kMaxNq];
+  double f[kMaxNq * 3];
+  double bn[kMaxNf][kMaxNfq];  // beta . n (outward) at face points
+  double g[kMaxNf][kMaxNfq];
+  int interior[kMaxNf];
+  double sigma;
+};
+
+__device__ inline double tau_cd(double bn) { return 0.5 * (sqrt(bn * bn + 4.0) - bn); }
+
+__device__ void load_element(const SetupArgs& a, int64_t e, bool all_interior, ElemData& d) {
+  const MeshInfo& m = a.mi;
+  const Coeffs& c = a.cf;
+  int ijk[3];
+  el_ijk(m, e, ijk);
+  for (int k = threadIdx.x; k < m.nq * m.dim; k += blockDim.x) {
+    int q = k / m.dim, ax = k % m.dim;
+    d.beta[q][ax] = c.beta_q ? c.beta_q[(e * m.nq + q) * m.dim + ax] : c.beta_const[ax];
+  }
+  for (int q = threadIdx.x; q < m.nq; q += blockDim.x)
+    d.divb[q] = c.divbeta_q ? c.divbeta_q[e * m.nq + q] : 0.0;
+  for (int k = threadIdx.x; k < m.nq * a.m_f; k += blockDim.x)
+    d.f[k] = c.f_q ? c.f_q[e * m.nq * a.m_f + k] : 0.0;
+  for (int k = threadIdx.x; k < m.nf * m.nfq; k += blockDim.x) {
+    int f = k / m.nfq, qf = k % m.nfq, ax = f >> 1;
+    int64_t fid = face_id(m, ijk, f);
+    double sg = face_sign(f);
+    d.bn[f][qf] = sg * (c.bn_fq ? c.bn_fq[fid * m.nfq + qf] : c.beta_const[ax]);
+    d.g[f][qf] = c.g_fq ? c.g_fq[fid * m.nfq + qf] : 0.0;
+  }
+  if (threadIdx.x < m.nf) d.interior[threadIdx.x] = all_interior || neighbour(m, ijk, threadIdx.x) >= 0;
+  if (threadIdx.x == 0) d.sigma = c.sigma_el ? c.sigma_el[e] : c.sigma_const;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// entries of L, E and F.  Row (fi, ni) = test function; column (fj, nj) = trial.
+// ---------------------------------------------------------------------------
+__device__ double mass(const Basis& b, int ni, int nj) {
+  double v = 0.0;
+  for (int q = 0; q < b.m.nq; ++q) v += b.W(q) * b.B(q, ni) * b.B(q, nj);
+  return v;
+}
+// (l_j, d_a l_i)
+__device__ double stiff(const Basis& b, int a, int ni, int nj) {
+  double v = 0.0;
+  for (int q = 0; q < b.m.nq; ++q) v += b.W(q) * b.B(q, nj) * b.D(a, q, ni);
+  return v;
+}
+// <w l_j, l_i>_f with w = 1 (wsel 0) or a per-point weight array
+__device__ double face_mass(const Basis& b, int f, int ni, int nj, const double* w) {
+  if (!b.on_face(f, ni) || !b.on_face(f, nj)) return 0.0;
+  double v = 0.0;
+  for (int qf = 0; qf < b.m.nfq; ++qf) v += b.Wf(f, qf) * (w ? w[qf] : 1.0) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+  return v;
+}
+// -(l_j, beta . grad l_i + (div beta) l_i)
+__device__ double convect(const Basis& b, const ElemData& d, int ni, int nj) {
+  double v = 0.0;
+  for (int q = 0; q < b.m.nq; ++q) {
+    double bg = 0.0;
+    for (int a = 0; a < b.m.dim; ++a) bg += d.beta[q][a] * b.D(a, q, ni);
+    v -= b.W(q) * b.B(q, nj) * (bg + d.divb[q] * b.B(q, ni));
+  }
+  return v;
+}
+
+__device__ double entry_L(const SetupArgs& a, const Basis& b, const ElemData& d, int row, int col) {
+  const int np = a.mi.np, dim = a.mi.dim;
+  const int fi = row / np, ni = row % np, fj = col / np, nj = col % np;
+  const Coeffs& c = a.cf;
+  if (a.pde == kTransport) {
+    // -(u, div(beta v)) + sigma (u, v) + <(beta.n + |beta.n|) u, v>
+    double v = convect(b, d, ni, nj) + d.sigma * mass(b, ni, nj);
+    for (int f = 0; f < a.mi.nf; ++f) {
+      if (!b.on_face(f, ni) || !b.on_face(f, nj)) continue;
+      for (int qf = 0; qf < a.mi.nfq; ++qf) {
+        double bn = d.bn[f][qf];
+        v += b.Wf(f, qf) * (bn + fabs(bn)) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+      }
+    }
+    return v;
+  }
+  if (a.pde == kShallowWater) {
+    const double Phi = c.Phi, sP = sqrt(c.Phi), cm = c.mass_coef;
+    double v = 0.0;
+    if (fi == 0) {
+      if (fj == 0) {
+        v = cm * mass(b, ni, nj);
+        for (int f = 0; f < 4; ++f) v += sP * face_mass(b, f, ni, nj, nullptr);
+      } else {
+        int ax = fj - 1;
+        v = -Phi * stiff(b, ax, ni, nj);
+        for (int f = 0; f < 4; ++f)
+          if ((f >> 1) == ax) v += Phi * face_sign(f) * face_mass(b, f, ni, nj, nullptr);
+      }
+    } else {
+      int axi = fi - 1;
+      if (fj == 0) {
+        v = -Phi * stiff(b, axi, ni, nj);
+      } else if (fj == fi) {
+        v = (cm + c.gamma) * Phi * mass(b, ni, nj);
+      } else {
+        // u-row: -f0 Phi (v, w2);  v-row: +f0 Phi (u, w3)
+        v = (fi == 1 ? -1.0 : 1.0) * c.f0 * Phi * mass(b, ni, nj);
+      }
+    }
+    return v;
+  }
+  // convection-diffusion, fields s_0..s_{dim-1}, u = dim
+  if (fi < dim) {
+    if (fj < dim) return (fi == fj) ? mass(b, ni, nj) / c.kappa : 0.0;
+    return -stiff(b, fi, ni, nj);  // -(u, d_a t)
+  }
+  if (fj < dim) {
+    double v = -stiff(b, fj, ni, nj);  // -(s_a, d_a v)
+    for (int f = 0; f < a.mi.nf; ++f)
+      if ((f >> 1) == fj) v += face_sign(f) * face_mass(b, f, ni, nj, nullptr);  // <s . n, v>
+    return v;
+  }
+  double v = convect(b, d, ni, nj) + c.nu * mass(b, ni, nj);
+  for (int f = 0; f < a.mi.nf; ++f) {
+    if (!b.on_face(f, ni) || !b.on_face(f, nj)) continue;
+    for (int qf = 0; qf < a.mi.nfq; ++qf) {
+      double bn = d.bn[f][qf];
+      v += b.Wf(f, qf) * (bn + tau_cd(bn)) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+    }
+  }
+  return v;
+}
+
+// E: column k = f * nfp + t feeds face-node value t of local face f.
+__device__ double entry_E(const SetupArgs& a, const Basis& b, const ElemData& d, int row, int k) {
+  const int np = a.mi.np, nfp = a.mi.nfp, dim = a.mi.dim;
+  const int fi = row / np, ni = row % np;
+  const int f = k / nfp, t = k % nfp, ax = f >> 1;
+  const int nj = fnode(a.mi.n1, dim, f, t);
+  if (!b.on_face(f, ni)) return 0.0;
+  const Coeffs& c = a.cf;
+  double w[kMaxNfq];
+  if (a.pde == kTransport) {
+    // weighted trace |beta.n| uhat on the face; on a boundary face only the outflow part
+    for (int qf = 0; qf < a.mi.nfq; ++qf) {
+      double bn = d.bn[f][qf];
+      w[qf] = d.interior[f] ? fabs(bn) : fmax(bn, 0.0);
+    }
+    return face_mass(b, f, ni, nj, w);
+  }
+  if (a.pde == kShallowWater) {
+    double fm = face_mass(b, f, ni, nj, nullptr);
+    if (fi == 0) return sqrt(c.Phi) * fm;
+    return (fi - 1 == ax) ? -c.Phi * face_sign(f) * fm : 0.0;
+  }
+  if (fi < dim) return (fi == ax) ? -face_sign(f) * face_mass(b, f, ni, nj, nullptr) : 0.0;
+  for (int qf = 0; qf < a.mi.nfq; ++qf) w[qf] = tau_cd(d.bn[f][qf]);
+  return face_mass(b, f, ni, nj, w);
+}
+
+__device__ double entry_F(const SetupArgs& a, const Basis& b, const ElemData& d, int row) {
+  const int np = a.mi.np, dim = a.mi.dim;
+  const int fi = row / np, ni = row % np;
+  double v = 0.0;
+  const bool has_f = (a.pde == kShallowWater) || (a.pde == kTransport) || (fi == dim);
+  if (has_f) {
+    const int comp = (a.pde == kShallowWater) ? fi : 0;
+    for (int q = 0; q < a.mi.nq; ++q) v += b.W(q) * d.f[q * a.m_f + comp] * b.B(q, ni);
+  }
+  if (a.pde == kShallowWater) return v;  // walls: no boundary data
+  for (int f = 0; f < a.mi.nf; ++f) {
+    if (d.interior[f] || !b.on_face(f, ni)) continue;
+    const int ax = f >> 1;
+    for (int qf = 0; qf < a.mi.nfq; ++qf) {
+      double bn = d.bn[f][qf], wq = b.Wf(f, qf) * b.Bf(f, qf, ni) * d.g[f][qf];
+      if (a.pde == kTransport) {
+        v += wq * fmax(-bn, 0.0);          // |beta.n| g on inflow points
+      } else if (fi < dim) {
+        if (fi == ax) v -= face_sign(f) * wq;  // -<g, t . n>
+      } else {
+        v += wq * tau_cd(bn);              // <tau g, v>
+      }
+    }
+  }
+  return v;
+}
+
+// Gauss-Jordan with partial pivoting on an n x ncol row-major matrix in global
+// memory; afterwards columns n..ncol-1 hold L^{-1} times the right-hand sides.
+__device__ void gauss_jordan(double* A, int n, int ncol, int* flag) {
+  __shared__ double colk[kMaxNloc];
+  __shared__ int piv;
+  __shared__ double pval;
+  for (int k = 0; k < n; ++k) {
+    if (threadIdx.x == 0) {
+      int best = k;
+      double bv = fabs(A[(int64_t)k * ncol + k]);
+      for (int i = k + 1; i < n; ++i) {
+        double v = fabs(A[(int64_t)i * ncol + k]);
+        if (v > bv) {
+          bv = v;
+          best = i;
+        }
+      }
+      piv = best;
+      pval = A[(int64_t)best * ncol + k];
+      if (!(bv > 1e-300) || !isfinite(bv)) atomicOr(flag, 1);
+    }
+    __syncthreads();
+    const int pr = piv;
+    const double inv = (pval != 0.0) ? 1.0 / pval : 0.0;
+    if (pr != k) {
+      for (int j = k + threadIdx.x; j < ncol; j += blockDim.x) {
+        double t = A[(int64_t)k * ncol + j];
+        A[(int64_t)k * ncol + j] = A[(int64_t)pr * ncol + j];
+        A[(int64_t)pr * ncol + j] = t;
+      }
+    }
+    __syncthreads();
+    for (int j = k + threadIdx.x; j < ncol; j += blockDim.x) A[(int64_t)k * ncol + j] *= inv;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = A[(int64_t)i * ncol + k];
+    __syncthreads();
+    const int w = ncol - k;
+    for (int idx = threadIdx.x; idx < n * w; idx += blockDim.x) {
+      int i = idx / w, j = k + idx % w;
+      if (i != k) A[(int64_t)i * ncol + j] -= colk[i] * A[(int64_t)k * ncol + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Conv.-diff. face projection of local face f: P = M_alpha^{-1} [M | M_{(alpha+bn)/2} | M_{(alpha-bn)/2}]
+// (nfp x 3 nfp, row-major), the weak form of the trace of the conservation condition.
+__device__ void cd_projection(const SetupArgs& a, const Basis& b, const ElemData& d, int f, double* out) {
+  const int nfp = a.mi.nfp, dim = a.mi.dim;
+  double Ma[49];     // conv.-diff. is 2-D: nfp <= 7
+  double R[7 * 21];
+  for (int cc = 0; cc < nfp; ++cc) {
+    int ic = fnode(a.mi.n1, dim, f, cc);
+    for (int bb = 0; bb < nfp; ++bb) {
+      int ib = fnode(a.mi.n1, dim, f, bb);
+      double m0 = 0, ma = 0, mp = 0, mm = 0;
+      for (int qf = 0; qf < a.mi.nfq; ++qf) {
+        double bn = d.bn[f][qf], al = sqrt(bn * bn + 4.0);
+        double w = b.Wf(f, qf) * b.Bf(f, qf, ib) * b.Bf(f, qf, ic);
+        m0 += w;
+        ma += w * al;
+        mm += w * 0.5 * (al + bn);
+        mp += w * 0.5 * (al - bn);
+      }
+      Ma[cc * nfp + bb] = ma;
+      R[cc * 3 * nfp + bb] = m0;
+      R[cc * 3 * nfp + nfp + bb] = mm;
+      R[cc * 3 * nfp + 2 * nfp + bb] = mp;
+    }
+  }
+  // solve Ma X = R (Gaussian elimination with partial pivoting, 3 nfp right-hand sides)
+  const int nr = 3 * nfp;
+  for (int k = 0; k < nfp; ++k) {
+    int best = k;
+    for (int i = k + 1; i < nfp; ++i)
+      if (fabs(Ma[i * nfp + k]) > fabs(Ma[best * nfp + k])) best = i;
+    if (best != k) {
+      for (int j = 0; j < nfp; ++j) {
+        double t = Ma[k * nfp + j];
+        Ma[k * nfp + j] = Ma[best * nfp + j];
+        Ma[best * nfp + j] = t;
+      }
+      for (int j = 0; j < nr; ++j) {
+        double t = R[k * nr + j];
+        R[k * nr + j] = R[best * nr + j];
+        R[best * nr + j] = t;
+      }
+    }
+    double inv = 1.0 / Ma[k * nfp + k];
+    for (int i = 0; i < nfp; ++i) {
+      if (i == k) continue;
+      double fct = Ma[i * nfp + k] * inv;
+      if (fct == 0.0) continue;
+      for (int j = k; j < nfp; ++j) Ma[i * nfp + j] -= fct * Ma[k * nfp + j];
+      for (int j = 0; j < nr; ++j) R[i * nr + j] -= fct * R[k * nr + j];
+    }
+  }
+  for (int i = 0; i < nfp; ++i) {
+    double inv = 1.0 / Ma[i * nfp + i];
+    for (int j = 0; j < nr; ++j) R[i * nr + j] *= inv;
+  }
+  // out layout: [3][nfp][nfp]: block s, row c, col b
+  for (int s = 0; s < 3; ++s)
+    for (int cc = 0; cc < nfp; ++cc)
+      for (int bb = 0; bb < nfp; ++bb) out[(s * nfp + cc) * nfp + bb] = R[cc * nr + s * nfp + bb];
+}
+
+__global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
+  __shared__ RefTab rt;
+  __shared__ ElemData d;
+  if (threadIdx.x == 0) rt = a.rt;
+  __syncthreads();
+  const MeshInfo& m = a.mi;
+  const int64_t le = blockIdx.x;
+  const int64_t e = a.e0 + le;
+  if (le >= a.count) return;
+  Basis b(rt, m);
+  const bool rep = a.shared_rep != 0;
+  load_element(a, e, rep, d);
+  const int n = a.n_loc, ni = a.n_in, nc = a.ncol;
+  double* A = a.scratch + le * (int64_t)n * nc;
+  for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
+    int r = idx / nc, col = idx % nc;
+    double v;
+    if (col < n) v = entry_L(a, b, d, r, col);
+    else if (col < n + ni) v = entry_E(a, b, d, r, col - n);
+    else if (!rep) v = entry_F(a, b, d, r);
+    else v = (col - n - ni == r) ? 1.0 : 0.0;  // identity: L^{-1}
+    A[idx] = v;
+  }
+  // conv.-diff. face projections
+  if (a.pde == kConvDiff && threadIdx.x < m.nf) {
+    const int f = threadIdx.x;
+    double P[3 * 49];
+    cd_projection(a, b, d, f, P);
+    const int np3 = 3 * m.nfp * m.nfp;
+    const int64_t blk = e / kLanes;
+    const int lane = (int)(e % kLanes);
+    for (int k = 0; k < np3; ++k) {
+      if (rep) {
+        a.P64[f * np3 + k] = P[k];
+        a.P32[f * np3 + k] = (float)P[k];
+      } else {
+        int64_t o = ((blk * m.nf + f) * np3 + k) * kLanes + lane;
+        a.P64[o] = P[k];
+        if (a.P32) a.P32[o] = (float)P[k];
+      }
+    }
+  }
+  __syncthreads();
+  gauss_jordan(A, n, nc, &a.flags[0]);
+  // outputs
+  if (rep) {
+    for (int idx = threadIdx.x; idx < n * ni; idx += blockDim.x) {
+      int r = idx / ni, j = idx % ni;
+      double v = A[(int64_t)r * nc + n + j];
+      a.G64[idx] = v;
+      a.G32[idx] = (float)v;
+    }
+    for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+      int r = idx / n, j = idx % n;
+      a.Linv[idx] = A[(int64_t)r * nc + n + ni + j];
+    }
+  } else {
+    const int64_t blk = e / kLanes;
+    const int lane = (int)(e % kLanes);
+    for (int idx = threadIdx.x; idx < n * ni; idx += blockDim.x) {
+      int r = idx / ni, j = idx % ni;
+      double v = A[(int64_t)r * nc + n + j];
+      int64_t o = ((blk * n + r) * ni + j) * kLanes + lane;
+      a.G64[o] = v;
+      if (a.G32) a.G32[o] = (float)v;
+    }
+    for (int r = threadIdx.x; r < n; r += blockDim.x) a.c64[(blk * n + r) * kLanes + lane] = A[(int64_t)r * nc + n + ni];
+  }
+}
+
+// Shared operator: c_K = L^{-1} F_K for every element (F_K assembled per element).
+__global__ __launch_bounds__(kST) void k_shared_c(SetupArgs a) {
+  __shared__ RefTab rt;
+  __shared__ ElemData d;
+  __shared__ double F[kMaxNloc];
+  if (threadIdx.x == 0) rt = a.rt;
+  __syncthreads();
+  const MeshInfo& m = a.mi;
+  const int64_t e = a.e0 + blockIdx.x;
+  if ((int64_t)blockIdx.x >= a.count) return;
+  Basis b(rt, m);
+  load_element(a, e, false, d);
+  const int n = a.n_loc;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) F[r] = entry_F(a, b, d, r);
+  __syncthreads();
+  const int64_t blk = e / kLanes;
+  const int lane = (int)(e % kLanes);
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += a.Linv[r * n + j] * F[j];
+    a.c64[(blk * n + r) * kLanes + lane] = s;
+  }
+}
+
+// Source map of the gather, fmap[blk][f][lane]:
+//   transport: the element whose trace feeds local face f (itself on an
+//     outflow face, its neighbour on an inflow face, -1 on an inflow boundary
+//     face).  An interior face on which beta.n changes sign raises flags[1].
+//   shallow water, conv.-diff.: the neighbour across f, or -1 on the boundary.
+__global__ void k_maps(SetupArgs a, int* fmap) {
+  const MeshInfo& m = a.mi;
+  const int64_t total = m.n_blk * kLanes * m.nf;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = k / m.nf;
+    const int f = (int)(k % m.nf);
+    const int64_t blk = e / kLanes;
+    const int lane = (int)(e % kLanes);
+    int v = -1;
+    if (e < m.n_el) {
+      int ijk[3];
+      el_ijk(m, e, ijk);
+      int64_t nb = neighbour(m, ijk, f);
+      if (a.pde == kTransport) {
+        const int ax = f >> 1;
+        const double sg = face_sign(f);
+        const int64_t fid = face_id(m, ijk, f);
+        bool pos = false, neg = false;
+        for (int qf = 0; qf < m.nfq; ++qf) {
+          double bn = sg * (a.cf.bn_fq ? a.cf.bn_fq[fid * m.nfq + qf] : a.cf.beta_const[ax]);
+          pos |= bn > 0.0;
+          neg |= bn < 0.0;
+        }
+        if (!neg) v = (int)e;                  // outflow (or tangential): own trace
+        else if (!pos) v = (int)nb;            // inflow: upwind neighbour, -1 on the boundary
+        else if (nb < 0) v = (int)e;           // mixed boundary face: own trace on outflow points
+        else {
+          atomicOr(&a.flags[1], 1);
+          v = (int)nb;
+        }
+      } else {
+        v = (int)nb;
+      }
+    }
+    fmap[(blk * m.nf + f) * kLanes + lane] = v;
+  }
+}
+
+__global__ void k_quad_points(MeshInfo m, RefTab t, double* xq, double* xfq) {
+  const int64_t nv = xq ? m.n_el * m.nq : 0;
+  const int64_t nfv = xfq ? m.n_face * m.nfq : 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nv + nfv; k += (int64_t)gridDim.x * blockDim.x) {
+    if (k < nv) {
+      int64_t e = k / m.nq;
+      int q = (int)(k % m.nq);
+      int ijk[3];
+      el_ijk(m, e, ijk);
+      int r = q;
+      for (int a = 0; a < m.dim; ++a) {
+        int qa = r % t.nq1;
+        r /= t.nq1;
+        xq[k * m.dim + a] = m.lo[a] + ijk[a] * m.h[a] + 0.5 * m.h[a] * (t.q[qa] + 1.0);
+      }
+    } else {
+      int64_t kk = k - nv;
+      int64_t fid = kk / m.nfq;
+      int qf = (int)(kk % m.nfq);
+      int ax = 0;
+      while (ax + 1 < m.dim && fid >= m.face_off[ax + 1]) ++ax;
+      int64_t loc = fid - m.face_off[ax];
+      int j[3] = {0, 0, 0};
+      for (int b = 0; b < m.dim; ++b) {
+        int64_t nb = m.n[b] + (b == ax ? 1 : 0);
+        j[b] = (int)(loc % nb);
+        loc /= nb;
+      }
+      int r = qf;
+      for (int b = 0; b < m.dim; ++b) {
+        double x;
+        if (b == ax) {
+          x = m.lo[b] + j[b] * m.h[b];
+        } else {
+          int qa = r % t.nq1;
+          r /= t.nq1;
+          x = m.lo[b] + j[b] * m.h[b] + 0.5 * m.h[b] * (t.q[qa] + 1.0);
+        }
+        xfq[kk * m.dim + b] = x;
+      }
+    }
+  }
+}
+
+hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_setup, dim3((unsigned)a.count), dim3(kST), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_shared_c(const SetupArgs& a, hipStream_t s) {
+  if (a.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shared_c, dim3((unsigned)a.count), dim3(kST), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_maps(const SetupArgs& a, int* fmap, hipStream_t s) {
+  int64_t total = a.mi.n_blk * kLanes * a.mi.nf;
+  unsigned blocks = (unsigned)((total + 255) / 256);
+  if (blocks > 65535u * 16u) blocks = 65535u * 16u;
+  hipLaunchKernelGGL(k_maps, dim3(blocks), dim3(256), 0, s, a, fmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_points(const MeshInfo& mi, const RefTab& rt, double* xq, double* xfq, hipStream_t s) {
+  int64_t total = (xq ? mi.n_el * mi.nq : 0) + (xfq ? mi.n_face * mi.nfq : 0);
+  if (total == 0) return hipSuccess;
+  unsigned blocks = (unsigned)((total + 255) / 256);
+  if (blocks > 65535u * 16u) blocks = 65535u * 16u;
+  hipLaunchKernelGGL(k_quad_points, dim3(blocks), dim3(256), 0, s, mi, rt, xq, xfq);
+  return hipGetLastError();
+}
+
+}  // namespace ihdg

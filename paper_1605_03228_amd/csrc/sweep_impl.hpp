@@ -1,0 +1,199 @@
+// The iHDG sweep kernel (one iteration of Algorithm 1 for a block of 64
+// elements), templated on precision, PDE, dimension and order.
+//
+//   (a) gather: for every local face, the face-node values of the previous
+//       iterate that the local solve needs (own trace, the neighbour's trace
+//       through the face map, or nothing on a boundary whose data is already
+//       in c_K), staged in LDS as x[n_in][64];
+//   (b) face step: the weighted trace of eq. iHDGtrace at the face nodes
+//       (transport: a selection, eq. uhk; shallow water: phihat = {{phi}} +
+//       sqrt(Phi) {{vel.n}}; conv.-diff.: the face projection of the
+//       conservation condition);
+//   (c) local solve u_K^{k+1} = c_K + G_K x_K (per-element G_K streamed from
+//       HBM in the interleaved layout, or one G shared by all elements);
+//   (d) write u^{k+1}, and the block's partial sums of
+//       w (u^{k+1} - u^k)^2 and w (u^{k+1})^2 for the h-norm.
+//
+// The same kernel runs the FP32 correction sweeps of the mixed-precision
+// path: then u is the correction, c the FP64 defect rounded to FP32, and G,
+// P the FP32 copies of the operators.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace ihdg {
+
+template <int PDE, int DIM>
+struct PdeTraits {
+  static constexpr int M = PDE == kTransport ? 1 : (PDE == kShallowWater ? 3 : DIM + 1);
+};
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <typename T, int PDE, int DIM, int P, bool SHARED>
+__device__ inline void face_step(const SweepArgs& a, int64_t blk, int f, int l, T* xs) {
+  constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
+  constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP;
+  const T* __restrict__ u = (const T*)a.uin;
+  const int s = a.fmap[(blk * NF + f) * kLanes + l];
+  T x[NFP];
+  if constexpr (PDE == kTransport) {
+    if (s < 0) {
+#pragma unroll
+      for (int t = 0; t < NFP; ++t) x[t] = T(0);
+    } else {
+      const int64_t e = blk * kLanes + l;
+      const int sf = (s == e) ? f : (f ^ 1);
+      const T* src = u + ((int64_t)(s >> 6) * NLOC) * kLanes + (s & 63);
+#pragma unroll
+      for (int t = 0; t < NFP; ++t) x[t] = src[fnode(N1, DIM, sf, t) * kLanes];
+    }
+  } else if constexpr (PDE == kShallowWater) {
+    const int ax = f >> 1;
+    const T sg = (f & 1) ? T(1) : T(-1);
+    const T sP = (T)a.sqrt_phi;
+    const T* own = u + (blk * NLOC) * kLanes + l;
+#pragma unroll
+    for (int t = 0; t < NFP; ++t) {
+      const int no = fnode(N1, DIM, f, t);
+      const T ph = own[no * kLanes];
+      const T vn = sg * own[((1 + ax) * NP + no) * kLanes];
+      if (s >= 0) {
+        const T* nb = u + ((int64_t)(s >> 6) * NLOC) * kLanes + (s & 63);
+        const int ni = fnode(N1, DIM, f ^ 1, t);
+        const T php = nb[ni * kLanes];
+        const T vnp = sg * nb[((1 + ax) * NP + ni) * kLanes];
+        x[t] = T(0.5) * (ph + php) + T(0.5) * sP * (vn - vnp);
+      } else {
+        x[t] = ph + sP * vn;  // wall: mirror state
+      }
+    }
+  } else {  // convection-diffusion
+    if (s < 0) {
+#pragma unroll
+      for (int t = 0; t < NFP; ++t) x[t] = T(0);
+    } else {
+      const int ax = f >> 1;
+      const T sg = (f & 1) ? T(1) : T(-1);
+      const T* own = u + (blk * NLOC) * kLanes + l;
+      const T* nb = u + ((int64_t)(s >> 6) * NLOC) * kLanes + (s & 63);
+      T ds[NFP], um[NFP], up[NFP];
+#pragma unroll
+      for (int t = 0; t < NFP; ++t) {
+        const int no = fnode(N1, DIM, f, t), ni = fnode(N1, DIM, f ^ 1, t);
+        ds[t] = sg * (own[(ax * NP + no) * kLanes] - nb[(ax * NP + ni) * kLanes]);
+        um[t] = own[(DIM * NP + no) * kLanes];
+        up[t] = nb[(DIM * NP + ni) * kLanes];
+      }
+      constexpr int NP3 = 3 * NFP * NFP;
+      const T* Pm = (const T*)a.P;
+      int64_t base;
+      int64_t str;
+      if constexpr (SHARED) {
+        base = (int64_t)f * NP3;
+        str = 1;
+      } else {
+        base = ((blk * NF + f) * NP3) * kLanes + l;
+        str = kLanes;
+      }
+#pragma unroll
+      for (int c = 0; c < NFP; ++c) {
+        T acc = T(0);
+#pragma unroll
+        for (int b = 0; b < NFP; ++b) {
+          acc += Pm[base + ((0 * NFP + c) * NFP + b) * str] * ds[b];
+          acc += Pm[base + ((1 * NFP + c) * NFP + b) * str] * um[b];
+          acc += Pm[base + ((2 * NFP + c) * NFP + b) * str] * up[b];
+        }
+        x[c] = acc;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NFP; ++t) xs[(f * NFP + t) * kLanes + l] = x[t];
+}
+
+template <typename T, int PDE, int DIM, int P, bool SHARED, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep(SweepArgs a) {
+  constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
+  constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
+  __shared__ T xs[NIN * kLanes];
+  __shared__ double red[2 * NW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t blk = blockIdx.x;
+
+  // (a) + (b)
+  for (int fl = tid; fl < NF * kLanes; fl += 64 * NW) face_step<T, PDE, DIM, P, SHARED>(a, blk, fl >> 6, fl & 63, xs);
+  __syncthreads();
+
+  // (c) + (d)
+  const T* __restrict__ uin = (const T*)a.uin;
+  T* __restrict__ uout = (T*)a.uout;
+  const T* __restrict__ cc = (const T*)a.c;
+  const T* __restrict__ G = (const T*)a.G;
+  double sd = 0.0, su = 0.0;
+  for (int r = w; r < NLOC; r += NW) {
+    const int64_t o = (blk * NLOC + r) * kLanes + lane;
+    T acc = cc[o];
+    if constexpr (SHARED) {
+      const T* g = G + r * NIN;
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) acc += g[j] * xs[j * kLanes + lane];
+    } else {
+      const T* g = G + (blk * NLOC + r) * (int64_t)NIN * kLanes + lane;
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) acc += g[j * kLanes] * xs[j * kLanes + lane];
+    }
+    const T old = uin[o];
+    uout[o] = acc;
+    const double dd = (double)acc - (double)old, wt = a.wnorm[r];
+    sd += wt * dd * dd;
+    su += wt * (double)acc * (double)acc;
+  }
+  sd = wave_sum(sd);
+  su = wave_sum(su);
+  if (lane == 0) {
+    red[w] = sd;
+    red[NW + w] = su;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < NW; ++i) {
+      s0 += red[i];
+      s1 += red[NW + i];
+    }
+    a.partials[2 * blk] = s0;
+    a.partials[2 * blk + 1] = s1;
+  }
+}
+
+template <typename T, int PDE, int DIM, int P, bool SHARED>
+hipError_t launch_one(int waves, const SweepArgs& a, hipStream_t s) {
+  dim3 grid((unsigned)a.n_blk);
+  switch (waves) {
+    case 1: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 1>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 2>), grid, dim3(128), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 8>), grid, dim3(512), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 4>), grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <int PDE, int DIM, int P>
+hipError_t launch_variants(bool fp32, bool shared, int waves, const SweepArgs& a, hipStream_t s) {
+  if (fp32) {
+    return shared ? launch_one<float, PDE, DIM, P, true>(waves, a, s)
+                  : launch_one<float, PDE, DIM, P, false>(waves, a, s);
+  }
+  return shared ? launch_one<double, PDE, DIM, P, true>(waves, a, s)
+                : launch_one<double, PDE, DIM, P, false>(waves, a, s);
+}
+
+}  // namespace ihdg

@@ -1,0 +1,161 @@
+// Small device kernels around the sweep: the fixed-order reduction of the
+// per-block norm partials, the FP64 -> FP32 defect, the FP64 update with an
+// FP32 correction, and conversion between the interleaved layout and the
+// element-major layout of the C ABI.
+#include "internal.hpp"
+
+namespace ihdg {
+
+// out2[j] = sum over blocks of partials[2 blk + j], summed in a fixed order
+// (strided per thread, then a fixed tree), so the result does not depend on
+// launch timing.
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ p, int64_t n_blk, double* out2) {
+  __shared__ double s0[256], s1[256];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < n_blk; i += 256) {
+    a += p[2 * i];
+    b += p[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out2[0] = s0[0];
+    out2[1] = s1[0];
+  }
+}
+
+__global__ void k_diff_to_f32(const double* __restrict__ a, const double* __restrict__ b, float* __restrict__ o,
+                              int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    o[i] = (float)(a[i] - b[i]);
+}
+
+__global__ void k_add_f32(double* __restrict__ u, const float* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    u[i] += (double)d[i];
+}
+
+template <typename T>
+__global__ void k_zero(T* x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = T(0);
+}
+
+// y = a*y + b*x
+__global__ void k_axpby(double* __restrict__ y, double a, const double* __restrict__ x, double b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * y[i] + b * x[i];
+}
+
+// interleaved [blk][row][lane] <-> user [el][row]
+__global__ void k_to_user(const double* __restrict__ il, double* __restrict__ us, int64_t n_el, int n_loc) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_el * n_loc;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = i / n_loc;
+    int r = (int)(i % n_loc);
+    us[i] = il[((e / kLanes) * n_loc + r) * kLanes + (e % kLanes)];
+  }
+}
+__global__ void k_from_user(const double* __restrict__ us, double* __restrict__ il, int64_t n_el, int n_loc) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_el * n_loc;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = i / n_loc;
+    int r = (int)(i % n_loc);
+    il[((e / kLanes) * n_loc + r) * kLanes + (e % kLanes)] = us[i];
+  }
+}
+
+// Weighted inner products <x, y_j>_h for j < k over the interleaved layout:
+// one partial per (block, j), then a fixed-order sum per j.
+__global__ __launch_bounds__(256) void k_dots_partial(const double* __restrict__ x, const double* const* ys, int k,
+                                                      const double* __restrict__ w, int n_loc, int64_t n_blk,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[4][16];
+  const int64_t blk = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int j = 0; j < k; ++j) {
+    double s = 0.0;
+    for (int r = wv; r < n_loc; r += 4) {
+      int64_t o = (blk * n_loc + r) * kLanes + lane;
+      s += w[r] * x[o] * ys[j][o];
+    }
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) red[wv][j & 15] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blk * k + j] = red[0][j & 15] + red[1][j & 15] + red[2][j & 15] + red[3][j & 15];
+    __syncthreads();
+  }
+}
+__global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ partial, int k, int64_t n_blk,
+                                                    double* out) {
+  __shared__ double s[256];
+  for (int j = 0; j < k; ++j) {
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n_blk; i += 256) a += partial[i * k + j];
+    s[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+      if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = s[0];
+    __syncthreads();
+  }
+}
+
+static unsigned grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 16384) b = 16384;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+hipError_t launch_reduce_partials(const double* partials, int64_t n_blk, double* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, n_blk, out2);
+  return hipGetLastError();
+}
+hipError_t launch_diff_to_f32(const double* a, const double* b, float* out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_diff_to_f32, dim3(grid_for(n)), dim3(256), 0, s, a, b, out, n);
+  return hipGetLastError();
+}
+hipError_t launch_add_f32_to_f64(double* u, const float* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f32, dim3(grid_for(n)), dim3(256), 0, s, u, d, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_zero_f32(float* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero<float>, dim3(grid_for(n)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_zero_f64(double* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero<double>, dim3(grid_for(n)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_to_user(const double* u_il, double* u_user, int64_t n_el, int n_loc, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_user, dim3(grid_for(n_el * n_loc)), dim3(256), 0, s, u_il, u_user, n_el, n_loc);
+  return hipGetLastError();
+}
+hipError_t launch_from_user(const double* u_user, double* u_il, int64_t n_el, int n_loc, hipStream_t s) {
+  hipLaunchKernelGGL(k_from_user, dim3(grid_for(n_el * n_loc)), dim3(256), 0, s, u_user, u_il, n_el, n_loc);
+  return hipGetLastError();
+}
+hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, s, y, a, x, b, n);
+  return hipGetLastError();
+}
+hipError_t launch_dots(const double* x, const double* const* ys, int k, const double* w, int n_loc, int64_t n_blk,
+                       double* partial, double* out, hipStream_t s) {
+  if (k > 16) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dots_partial, dim3((unsigned)n_blk), dim3(256), 0, s, x, ys, k, w, n_loc, n_blk, partial);
+  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, partial, k, n_blk, out);
+  return hipGetLastError();
+}
+
+}  // namespace ihdg

@@ -1,0 +1,167 @@
+"""GPU parity: the HIP sweep and solvers against the FP64 CPU oracle.
+
+Per-sweep parity: a sweep is a fixed linear map, so k sweeps from u^0 = 0 must
+agree with the oracle's k sweeps to rounding (tolerance 1e-12 relative in the
+h-norm).  Converged parity: the GPU iterate at tolerance 1e-12 must match the
+oracle's HDG solution (direct trace solve or downwind substitution) to 1e-10
+relative (FP64) or 1e-8 (mixed precision).  Sizes span several 64-element
+blocks and ragged last blocks.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle.convdiff import CDOperators
+from oracle.norms import h_norm
+from oracle.shallow_water import SWOperators
+from oracle.transport import TransportOperators
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_03228_amd import binding
+    binding.load()
+
+
+def oracle_for(pr):
+    return {"transport": TransportOperators, "sw": SWOperators, "cd": CDOperators}[pr.pde](pr)
+
+
+def gpu_solver(pr, **kw):
+    from paper_1605_03228_amd.problem_io import make_solver
+    print(f"[gpu] {pr.name} n={pr.n} p={pr.p} {kw}", flush=True)
+    return make_solver(pr, **kw)
+
+
+def rel(o, a, b):
+    return h_norm(o.mesh, o.el, a - b) / h_norm(o.mesh, o.el, b)
+
+
+def gpu_u(s):
+    u = s.get_solution()
+    torch.cuda.synchronize()
+    return u.reshape(u.shape[0], -1).cpu().numpy()
+
+
+CASES = [
+    ("cfg1_shared", lambda: w.config1(), {}),
+    ("cfg1_per_element", lambda: w.config1(), {"shared": False}),
+    ("cfg2_16x16_p4", lambda: w.config2(n=16, p=4), {}),
+    ("cfg2_ragged_13x11_p3", lambda: w.Problem(**{**w.config2(n=13, p=3).__dict__, "n": (13, 11),
+                                                   "sigma_el": w.config2(n=13, p=3).sigma_el[:143]}), {}),
+    ("affine_div_beta_9x7_p2", lambda: w.transport_affine_beta((9, 7), 2), {}),
+    ("cfg3_5cube_p3", lambda: w.config3(n=5, p=3), {}),
+    ("cfg3_4cube_p2_per_el", lambda: w.config3(n=4, p=2), {"shared": False}),
+    ("sw_10x10_p3", lambda: w.sw_standing_wave((10, 10), 3, f0=0.37), {}),
+    ("sw_9x7_p1", lambda: w.sw_standing_wave((9, 7), 1, f0=0.8), {}),
+    ("cd_9x9_p2_eps1e-4", lambda: w.cd_smooth((9, 9), 2, kappa=1e-4), {}),
+    ("cd_8x8_p4_eps1e-4", lambda: w.cd_smooth((8, 8), 4, kappa=1e-4), {}),
+    ("cd_const_6x6_p3", lambda: w.cd_poly((6, 6), 3, kappa=1e-3, affine_beta=False), {}),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_per_sweep_parity(name, make, kw):
+    pr = make()
+    o = oracle_for(pr)
+    s = gpu_solver(pr, **kw)
+    u = np.zeros((o.mesh.n_el, s.sz["n_loc"]))
+    for k in [1, 2, 3, 7]:
+        s.sweep(k - (0 if k == 1 else prev))
+        for _ in range(k - (0 if k == 1 else prev)):
+            u = o.sweep(u)
+        prev = k
+        ug = gpu_u(s)
+        r = rel(o, ug, u)
+        assert r < 1e-12, (k, r)
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_converged_parity_fp64(name, make, kw):
+    pr = make()
+    o = oracle_for(pr)
+    s = gpu_solver(pr, **kw)
+    res = s.solve(1e-12)
+    assert res["status"] == 0, res
+    ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
+    ug = gpu_u(s)
+    assert rel(o, ug, ref) < 1e-10
+    assert res["defect"] < 1e-11
+
+
+@pytest.mark.parametrize("name,make", [("cfg2_16x16_p4", lambda: w.config2(n=16, p=4)),
+                                       ("cfg3_5cube_p3", lambda: w.config3(n=5, p=3)),
+                                       ("sw_10x10_p3", lambda: w.sw_standing_wave((10, 10), 3, f0=0.37)),
+                                       ("cd_8x8_p4_eps1e-4", lambda: w.cd_smooth((8, 8), 4, kappa=1e-4))])
+def test_converged_parity_mixed(name, make):
+    pr = make()
+    o = oracle_for(pr)
+    s = gpu_solver(pr, prec=1)
+    res = s.solve(1e-10)
+    assert res["status"] == 0, res
+    ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
+    err = rel(o, gpu_u(s), ref)
+    print(f"mixed {name}: err {err:.3e} fp64 {res['fp64_sweeps']} fp32 {res['fp32_sweeps']} outer {res['outer_steps']}")
+    assert err < 1e-8
+
+
+def test_gmres_where_ihdg_diverges():
+    """Conv.-diff. at kappa = 1e-2, p = 4: plain iHDG diverges, GMRES with the sweep converges."""
+    pr = w.cd_smooth((6, 6), 4, kappa=1e-2)
+    o = oracle_for(pr)
+    s = gpu_solver(pr)
+    res = s.solve(1e-12)
+    assert res["status"] == 6  # diverged
+    s2 = gpu_solver(pr, krylov_restart=15)
+    res2 = s2.solve(1e-12)
+    assert res2["status"] == 0, res2
+    assert rel(o, gpu_u(s2), o.direct_hdg()) < 1e-9
+
+
+def test_mixed_sign_interior_face_rejected():
+    """beta = (0.5 - y, 1) on 3x3 quads: beta.n changes sign inside the x-faces that
+    straddle y = 0.5 -> unsupported (such a face needs both traces)."""
+    from paper_1605_03228_amd import binding
+    pr = w.Problem(pde="transport", dim=2, n=(3, 3), p=2,
+                   beta=lambda x, xp=np: xp.stack([0.5 - x[..., 1], x[..., 0] * 0 + 1.0], -1),
+                   sigma_const=1.0, forcing=lambda x, s, xp=np: (x[..., 0] * 0)[..., None],
+                   bdry=lambda x, xp=np: (x[..., 0] * 0)[..., None])
+    with pytest.raises(binding.IhdgError) as e:
+        gpu_solver(pr)
+    assert e.value.status == 2
+
+
+def test_set_get_solution_roundtrip_and_warm_start():
+    pr = w.config2(n=10, p=3)
+    s = gpu_solver(pr)
+    s.solve(1e-12)
+    u = s.get_solution().clone()
+    s2 = gpu_solver(pr)
+    s2.set_solution(u)
+    res = s2.solve(1e-12)
+    assert res["iters"] <= 16
+    assert torch.equal(s2.get_solution().cpu(), u.cpu()) or rel(
+        oracle_for(pr), gpu_u(s2), u.reshape(u.shape[0], -1).cpu().numpy()) < 1e-12
+
+
+def test_graph_and_direct_launches_agree_bitwise():
+    pr = w.config2(n=12, p=4)
+    a = gpu_solver(pr, use_graph=True, check_every=8)
+    b = gpu_solver(pr, use_graph=False, check_every=8)
+    ra, rb = a.solve(1e-12), b.solve(1e-12)
+    assert ra["iters"] == rb["iters"]
+    assert torch.equal(a.get_solution(), b.get_solution())
+
+
+def test_sweep_is_deterministic():
+    pr = w.cd_smooth((12, 12), 3, kappa=1e-4)
+    a, b = gpu_solver(pr), gpu_solver(pr)
+    na = a.sweep(9, norms=True)
+    nb = b.sweep(9, norms=True)
+    assert na == nb
+    assert torch.equal(a.get_solution(), b.get_solution())
