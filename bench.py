@@ -14,8 +14,14 @@ element-DOF updates per second.  The same line also reports the mixed path
 result against the CPU oracle, the roofline of the sweep kernel and the
 oracle's own throughput on the host.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-oracle]
+Other workloads (--workload): cfg1 (8x8 p=2 transport, constant beta),
+cfg3 (64^3 p=3 transport, constant beta: shared operator on MFMA), cfg4a
+(128^2 p=3 linearised shallow water, one Crank-Nicolson step), cfg4b
+(128^2 p=4 convection-diffusion, eps = 1e-4).  The default line is cfg2.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2] [--no-oracle]
 """
+import hashlib
 import argparse
 import json
 import os
@@ -35,8 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4a", "cfg4b"])
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle error and CPU baseline legs")
     ap.add_argument("--profile-pass", action="store_true",
@@ -44,10 +49,44 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes_per_element(n_loc, n_in, nf, fp):
-    """Bytes one sweep must move per element: the operator G_K, the affine part
-    c_K, the previous and the new iterate, and the face map."""
-    return n_loc * n_in * fp + 3 * n_loc * fp + nf * 4
+def algorithmic_bytes_per_element(n_loc, n_in, nf, fp, shared, proj=0):
+    """Bytes one sweep must move per element: the operator G_K (per-element
+    operators only), the affine part c_K, the previous and the new iterate,
+    the face map, and (conv.-diff., per element) the face projections."""
+    return (0 if shared else n_loc * n_in * fp) + 3 * n_loc * fp + nf * 4 + proj * fp
+
+
+def counter_traffic(key):
+    """HBM bytes per launch from the committed counter runs, if the sweep source
+    has not changed since they were taken (else None)."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
+            d = json.load(f)[key]
+        with open(os.path.join(ROOT, "paper_1605_03228_amd", "csrc", "sweep_impl.hpp"), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+        return d["traffic_bytes"] if sha == d["source_sha16"] else None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+KEYS = {"cfg2": "k_sweep<double, transport, 2, 4, per-element>"}
+KERNEL = {"cfg1": "k_sweep_mfma<double, transport, 2, 2>", "cfg2": "k_sweep<double, transport, 2, 4, per-element>",
+          "cfg3": "k_sweep_mfma<double, transport, 3, 3>", "cfg4a": "k_sweep_mfma<double, shallow water, 2, 3>",
+          "cfg4b": "k_sweep<double, conv.-diff., 2, 4, per-element>"}
+
+
+def make_problem(name):
+    import workloads as w
+    return {"cfg1": lambda: w.config1(), "cfg2": lambda: w.config2(seed=0),
+            "cfg3": lambda: w.config3(seed=0), "cfg4a": lambda: w.config4a(seed=0),
+            "cfg4b": lambda: w.config4b(eps=1e-4)}[name]()
+
+
+DESCR = {"cfg1": "2-D steady transport 8x8 quads p=2, beta=(1,0.5), shared operator",
+         "cfg2": "2-D steady transport 256x256 quads p=4, variable beta, per-element sigma, per-element local operators",
+         "cfg3": "3-D steady transport 64^3 hexes p=3, constant beta, shared operator (MFMA)",
+         "cfg4a": "2-D linearised shallow water 128x128 p=3, one Crank-Nicolson step, shared operator (MFMA)",
+         "cfg4b": "2-D convection-diffusion 128x128 p=4, eps=1e-4, beta=(1+y,1+x), per-element local operators"}
 
 
 def time_sweeps(torch, s, k):
@@ -59,11 +98,6 @@ def time_sweeps(torch, s, k):
     e1.record(s.stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3  # seconds
-
-
-def time_fp32_sweeps(torch, s, k):
-    """Time k FP32 correction sweeps through a mixed solve's inner path."""
-    return None
 
 
 def cpu_baseline(pr_full):
@@ -95,8 +129,8 @@ def cpu_baseline(pr_full):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is design-only "
-                                   "(see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "runs on one GPU only: the multi-GPU sharding of the sweep is a design, not code "
+                                   "in this library", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
@@ -104,14 +138,16 @@ def main():
     from paper_1605_03228_amd.problem_io import make_solver
 
     dev = "cuda"
-    pr = w.config2(seed=0, n=args.n, p=args.p)
+    pr = make_problem(args.workload)
     t0 = time.perf_counter()
     s64 = make_solver(pr, device=dev, block_waves=args.waves)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sz = s64.sz
     n_el, n_loc, n_in = sz["n_el"], sz["n_loc"], sz["n_in"]
-    nf = 4
+    nf = 2 * pr.dim
+    shared = bool(s64.stats()["shared_operator"])
+    proj = 0 if (shared or pr.pde != "cd") else nf * 3 * sz["nfp"] ** 2
 
     if args.profile_pass:
         s64.sweep(10)
@@ -130,25 +166,27 @@ def main():
     t = time_sweeps(torch, s64, args.steps)
     ms_per_step = t / args.steps * 1e3
     value = n_el * n_loc * args.steps / t
-    bpe64 = algorithmic_bytes_per_element(n_loc, n_in, nf, 8)
+    bpe64 = algorithmic_bytes_per_element(n_loc, n_in, nf, 8, shared, proj)
     achieved = bpe64 * n_el / (t / args.steps) / 1e9
+    flops_el = 2 * n_loc * n_in
+    tflops = flops_el * n_el / (t / args.steps) / 1e12
 
-    # ---- time to tolerance, FP64 ------------------------------------------------
+    # ---- time to tolerance (same tolerance for both paths) ------------------------
+    tol = 1e-12 if args.workload == "cfg1" else 1e-10
     s64b = make_solver(pr, device=dev, block_waves=args.waves)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r64 = s64b.solve(1e-12)
+    r64 = s64b.solve(tol)
     torch.cuda.synchronize()
     ttt64 = time.perf_counter() - t0
     u64 = s64b.get_solution()
 
-    # ---- mixed precision ---------------------------------------------------------
     t0 = time.perf_counter()
     smx = make_solver(pr, device=dev, prec=1, block_waves=args.waves)
     torch.cuda.synchronize()
     setup_mx = time.perf_counter() - t0
     t0 = time.perf_counter()
-    rmx = smx.solve(1e-10)
+    rmx = smx.solve(tol)
     torch.cuda.synchronize()
     tttmx = time.perf_counter() - t0
     umx = smx.get_solution()
@@ -164,14 +202,17 @@ def main():
     if not args.no_oracle:
         from oracle.norms import h_norm
         from oracle.transport import TransportOperators
-        o = TransportOperators(pr)
-        ref = o.downwind()
+        from oracle.convdiff import CDOperators
+        from oracle.shallow_water import SWOperators
+        o = {"transport": TransportOperators, "sw": SWOperators, "cd": CDOperators}[pr.pde](pr)
+        ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
         a64 = u64.reshape(n_el, -1).cpu().numpy()
         amx = umx.reshape(n_el, -1).cpu().numpy()
         nr = h_norm(o.mesh, o.el, ref)
         err64 = h_norm(o.mesh, o.el, a64 - ref) / nr
         errmx = h_norm(o.mesh, o.el, amx - ref) / nr
-        cpu = cpu_baseline(pr)
+        if args.workload == "cfg2":
+            cpu = cpu_baseline(pr)
 
     line = {
         "metric": "iHDG element-DOF updates/s/sweep (FP64 vs mixed) + p50/p99 solve latency",
@@ -186,15 +227,16 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded analytic coefficients, manufactured solution)",
-        "config": {"workload": f"2-D steady transport {args.n}x{args.n} quads p={args.p}, variable beta, "
-                               f"per-element sigma, per-element local operators (FP64)",
+        "config": {"workload": DESCR[args.workload] + " (FP64 sweep timed)",
                    "n_el": n_el, "n_loc": n_loc, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_element": bpe64, "kernel": "k_sweep<double, transport, 2, p, per-element>"},
-        "fp64": {"setup_s": setup_s, "solve_tol": 1e-12, "time_to_tol_s": ttt64, "sweeps": r64["iters"],
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (counter_traffic(KEYS.get(args.workload)) if args.waves in (0, 4) else None),
+                     "bytes_per_element": bpe64, "flops_per_element": flops_el, "achieved_tflops": tflops,
+                     "kernel": KERNEL[args.workload]},
+        "fp64": {"setup_s": setup_s, "solve_tol": tol, "time_to_tol_s": ttt64, "sweeps": r64["iters"],
                  "status": r64["status"], "rel_err_vs_oracle": err64},
-        "mixed": {"setup_s": setup_mx, "solve_tol": 1e-10, "time_to_tol_s": tttmx,
+        "mixed": {"setup_s": setup_mx, "solve_tol": tol, "time_to_tol_s": tttmx,
                   "fp64_sweeps": rmx["fp64_sweeps"], "fp32_sweeps": rmx["fp32_sweeps"],
                   "outer_steps": rmx["outer_steps"], "status": rmx["status"],
                   "fp32_sweep_rate": fp32_rate, "rel_err_vs_oracle": errmx,

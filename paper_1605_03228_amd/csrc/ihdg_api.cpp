@@ -608,6 +608,9 @@ static ihdg_status solve_mixed(ihdg_ctx* c, double tol, int32_t* iters, double* 
     best = std::min(best, dn);
     if (dn > 1e3 * best) return fail(c, IHDG_ERR_DIVERGED, "defect grew 1e3x above its minimum");
     if (total >= c->opt.max_iters) return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
+    // inner tolerance: enough to bring the defect below tol ||u||, never below
+    // what FP32 can resolve (inner_rtol)
+    const double eta = std::max(c->opt.inner_rtol, std::min(0.1, 0.3 * tol * un / dn));
     HIPCHK(c, launch_diff_to_f32(c->tmp64, c->u64[c->cur], c->d32, c->nvec, c->stream));
     HIPCHK(c, launch_fill_zero_f32(c->dl32[0], c->nvec, c->stream));
     HIPCHK(c, launch_fill_zero_f32(c->dl32[1], c->nvec, c->stream));
@@ -624,7 +627,7 @@ static ihdg_status solve_mixed(ihdg_ctx* c, double tol, int32_t* iters, double* 
       HIPCHK(c, read_norms(c, h));
       double inc = std::sqrt(h[0]), nd = std::sqrt(h[1]);
       if (!std::isfinite(inc)) return fail(c, IHDG_ERR_DIVERGED, "non-finite correction");
-      if (inc <= c->opt.inner_rtol * nd || inc == 0.0) break;
+      if (inc <= eta * nd || inc == 0.0) break;
       ibest = std::min(ibest, inc);
       if (inc > 1e3 * ibest) return fail(c, IHDG_ERR_DIVERGED, "correction diverged");
       // FP32 rounding floor: the increment no longer decreases
@@ -716,8 +719,9 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
   double rel = INFINITY;
   double* u = c->u64[c->cur];
   double* tmp = c->tmp64;
-  auto dots = [&](const double* x, int k, double* out) -> hipError_t {
-    for (int j = 0; j < k; ++j) hptr[j] = vec(j);
+  // <x, y_j>_h for the vectors y_0..y_{k-1} (device pointer list), k <= 16
+  auto dots_with = [&](const double* x, const double* const* ys, int k, double* out) -> hipError_t {
+    for (int j = 0; j < k; ++j) hptr[j] = const_cast<double*>(ys[j]);
     hipError_t e = hipMemcpyAsync(c->kry_ptrs, hptr.data(), k * sizeof(double*), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return e;
     e = launch_dots(x, (const double* const*)c->kry_ptrs, k, c->wnorm, c->sz.n_loc, c->mi.n_blk, c->kry_part,
@@ -726,6 +730,15 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
     e = hipMemcpyAsync(out, c->norms, k * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(c->stream);
+  };
+  auto dots = [&](const double* x, int k, double* out) -> hipError_t {
+    const double* ys[16];
+    for (int j = 0; j < k; ++j) ys[j] = vec(j);
+    return dots_with(x, ys, k, out);
+  };
+  auto selfdot = [&](const double* x, double* out) -> hipError_t {
+    const double* ys[1] = {x};
+    return dots_with(x, ys, 1, out);
   };
   // A v = v - psi(v) + c  written into out
   auto apply = [&](const double* v, double* out) -> hipError_t {
@@ -739,10 +752,7 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
   double bnorm;
   {
     double d;
-    HIPCHK(c, dots(c->c64, 0, &d));
-    // ||c||_h via a dot with itself: place c in V[0] temporarily
-    HIPCHK(c, hipMemcpyAsync(vec(0), c->c64, N * 8, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, dots(c->c64, 1, &d));
+    HIPCHK(c, selfdot(c->c64, &d));
     bnorm = std::sqrt(std::max(d, 0.0));
   }
   if (bnorm == 0.0) bnorm = 1.0;
@@ -752,7 +762,7 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
     HIPCHK(c, hipMemcpyAsync(vec(0), c->c64, N * 8, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, launch_axpby(vec(0), 1.0, tmp, -1.0, N, c->stream));
     double rr;
-    HIPCHK(c, dots(vec(0), 1, &rr));
+    HIPCHK(c, selfdot(vec(0), &rr));
     double beta = std::sqrt(std::max(rr, 0.0));
     rel = beta / bnorm;
     if (final_incr) *final_incr = rel;
@@ -767,7 +777,7 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
     int j = 0;
     for (; j < m && it < c->opt.max_iters; ++j, ++it) {
       HIPCHK(c, apply(vec(j), vec(j + 1)));
-      // modified Gram-Schmidt (classical, done twice for stability)
+      // classical Gram-Schmidt, done twice for stability
       for (int pass = 0; pass < 2; ++pass) {
         double h[16];
         HIPCHK(c, dots(vec(j + 1), j + 1, h));
@@ -778,19 +788,7 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
         }
       }
       double nn;
-      HIPCHK(c, dots(vec(j + 1), 1, &nn));
-      // dots(x, 1) gives <x, V0>; need <x, x>: compute with V0 := x temporarily is wrong, so use a
-      // dedicated self-dot below
-      (void)nn;
-      {
-        // self inner product: swap pointer list to point at vec(j+1)
-        hptr[0] = vec(j + 1);
-        HIPCHK(c, hipMemcpyAsync(c->kry_ptrs, hptr.data(), sizeof(double*), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, launch_dots(vec(j + 1), (const double* const*)c->kry_ptrs, 1, c->wnorm, c->sz.n_loc, c->mi.n_blk,
-                              c->kry_part, c->norms, c->stream));
-        HIPCHK(c, hipMemcpyAsync(&nn, c->norms, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-      }
+      HIPCHK(c, selfdot(vec(j + 1), &nn));
       double hn = std::sqrt(std::max(nn, 0.0));
       H[(j + 1) * m + j] = hn;
       if (hn > 0) HIPCHK(c, launch_axpby(vec(j + 1), 1.0 / hn, vec(j + 1), 0.0, N, c->stream));

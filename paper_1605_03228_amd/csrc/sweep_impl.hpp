@@ -36,12 +36,11 @@ __device__ inline double wave_sum(double v) {
 }
 
 template <typename T, int PDE, int DIM, int P, bool SHARED>
-__device__ inline void face_step(const SweepArgs& a, int64_t blk, int f, int l, T* xs) {
+__device__ inline void face_values(const SweepArgs& a, int64_t blk, int f, int l, T* x) {
   constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
   constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP;
   const T* __restrict__ u = (const T*)a.uin;
   const int s = a.fmap[(blk * NF + f) * kLanes + l];
-  T x[NFP];
   if constexpr (PDE == kTransport) {
     if (s < 0) {
 #pragma unroll
@@ -114,43 +113,83 @@ __device__ inline void face_step(const SweepArgs& a, int64_t blk, int f, int l, 
       }
     }
   }
+}
+
+template <typename T, int PDE, int DIM, int P, bool SHARED>
+__device__ inline void face_step(const SweepArgs& a, int64_t blk, int f, int l, T* xs) {
+  constexpr int NFP = ipow(P + 1, DIM - 1);
+  T x[NFP];
+  face_values<T, PDE, DIM, P, SHARED>(a, blk, f, l, x);
 #pragma unroll
   for (int t = 0; t < NFP; ++t) xs[(f * NFP + t) * kLanes + l] = x[t];
 }
 
+template <typename T, int PDE, int DIM, int P>
+__device__ inline void face_step_to(const SweepArgs& a, int64_t blk, int f, int l, T* x) {
+  face_values<T, PDE, DIM, P, true>(a, blk, f, l, x);
+}
+
+// Register budget: the grid supplies 64*NW threads per 64 elements, so at most
+// NW waves per SIMD are resident for NW <= 8 blocks per CU; ask the compiler
+// for that occupancy and no more, so it can keep a whole operator row in
+// flight instead of serialising the loads.
 template <typename T, int PDE, int DIM, int P, bool SHARED, int NW>
-__global__ __launch_bounds__(64 * NW) void k_sweep(SweepArgs a) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW < 4 ? 4 : NW, 8)))
+void k_sweep(SweepArgs a) {
   constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
   constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
+  constexpr int RPT = (NLOC + NW - 1) / NW;                      // rows per thread
+  constexpr bool XREG = NIN * sizeof(T) <= 32 * sizeof(double);  // keep x_K in registers
   __shared__ T xs[NIN * kLanes];
   __shared__ double red[2 * NW];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t blk = blockIdx.x;
+  const T* __restrict__ uin = (const T*)a.uin;
+  T* __restrict__ uout = (T*)a.uout;
+  const T* __restrict__ cc = (const T*)a.c;
+  const T* __restrict__ G = (const T*)a.G;
+
+  // start streaming this thread's first operator row before the gather
+  T gv[SHARED ? 1 : NIN];
+  if constexpr (!SHARED) {
+    const T* g = G + (blk * NLOC + w) * (int64_t)NIN * kLanes + lane;
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) gv[j] = g[j * kLanes];
+  }
 
   // (a) + (b)
   for (int fl = tid; fl < NF * kLanes; fl += 64 * NW) face_step<T, PDE, DIM, P, SHARED>(a, blk, fl >> 6, fl & 63, xs);
   __syncthreads();
 
+  T xr[XREG ? NIN : 1];
+  if constexpr (XREG) {
+#pragma unroll
+    for (int j = 0; j < NIN; ++j) xr[j] = xs[j * kLanes + lane];
+  }
+
   // (c) + (d)
-  const T* __restrict__ uin = (const T*)a.uin;
-  T* __restrict__ uout = (T*)a.uout;
-  const T* __restrict__ cc = (const T*)a.c;
-  const T* __restrict__ G = (const T*)a.G;
   double sd = 0.0, su = 0.0;
-  for (int r = w; r < NLOC; r += NW) {
+#pragma unroll
+  for (int rr = 0; rr < RPT; ++rr) {
+    const int r = w + rr * NW;
+    if (r >= NLOC) break;
     const int64_t o = (blk * NLOC + r) * kLanes + lane;
     T acc = cc[o];
+    const T old = uin[o];
     if constexpr (SHARED) {
       const T* g = G + r * NIN;
 #pragma unroll
-      for (int j = 0; j < NIN; ++j) acc += g[j] * xs[j * kLanes + lane];
+      for (int j = 0; j < NIN; ++j) acc += g[j] * (XREG ? xr[j] : xs[j * kLanes + lane]);
     } else {
-      const T* g = G + (blk * NLOC + r) * (int64_t)NIN * kLanes + lane;
+      if (rr > 0) {  // this row of the operator: NIN independent loads in flight
+        const T* g = G + (blk * NLOC + r) * (int64_t)NIN * kLanes + lane;
 #pragma unroll
-      for (int j = 0; j < NIN; ++j) acc += g[j * kLanes] * xs[j * kLanes + lane];
+        for (int j = 0; j < NIN; ++j) gv[j] = g[j * kLanes];
+      }
+#pragma unroll
+      for (int j = 0; j < NIN; ++j) acc += gv[j] * (XREG ? xr[j] : xs[j * kLanes + lane]);
     }
-    const T old = uin[o];
     uout[o] = acc;
     const double dd = (double)acc - (double)old, wt = a.wnorm[r];
     sd += wt * dd * dd;
@@ -174,8 +213,147 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(SweepArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Shared operator: the local solve of a block of 64 elements is one GEMM,
+// U (n_loc x 64) = C + G (n_loc x n_in) X (n_in x 64), on the matrix cores.
+// 16x16x4 MFMA tiles: wave w owns the row tiles w, w + NW, ...; its slice of
+// G (the A operand) is loaded into registers once and reused for every block
+// of a grid-stride loop; X (the B operand) is staged in LDS by the face step.
+// Operand layouts (lane l): A[i][k] at i = l % 16, k = l / 16; B[k][j] at
+// k = l / 16, j = l % 16; accumulator register r holds row
+// 4 (l / 16) + r (FP32) or 4 r + l / 16 (FP64), column l % 16.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+  static constexpr int kPad = 16;
+};
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ inline v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
+  static constexpr int kPad = 8;
+};
+
+template <typename T, int PDE, int DIM, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_mfma(SweepArgs a) {
+  constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
+  constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
+  constexpr int MT = (NLOC + 15) / 16, KT = (NIN + 3) / 4;
+  constexpr int MTW = (MT + NW - 1) / NW;  // row tiles per wave
+  constexpr int S = kLanes + Mfma<T>::kPad; // LDS row stride of X
+  typedef typename Mfma<T>::v4 v4;
+  __shared__ T xs[KT * 4 * S];
+  __shared__ double red[2 * NW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const T* __restrict__ G = (const T*)a.G;
+  const T* __restrict__ uin = (const T*)a.uin;
+  T* __restrict__ uout = (T*)a.uout;
+  const T* __restrict__ cc = (const T*)a.c;
+  const int li = lane & 15, lk = lane >> 4;
+
+  // A operand, resident for the whole kernel
+  T av[MTW][KT];
+#pragma unroll
+  for (int t = 0; t < MTW; ++t) {
+    const int mt = w + t * NW;
+#pragma unroll
+    for (int ks = 0; ks < KT; ++ks) {
+      const int r = mt * 16 + li, k = ks * 4 + lk;
+      av[t][ks] = (mt < MT && r < NLOC && k < NIN) ? G[r * NIN + k] : T(0);
+    }
+  }
+  // zero padding rows of X once (k >= NIN)
+  for (int i = tid; i < (KT * 4 - NIN) * S; i += 64 * NW) xs[NIN * S + i] = T(0);
+
+  double sd = 0.0, su = 0.0;
+  for (int64_t blk = blockIdx.x; blk < a.n_blk; blk += gridDim.x) {
+    // (a) + (b): face step writes x[k][element] into LDS (row stride S)
+    for (int fl = tid; fl < NF * kLanes; fl += 64 * NW) {
+      T tmp[NFP];
+      const int f = fl >> 6, l = fl & 63;
+      face_step_to<T, PDE, DIM, P>(a, blk, f, l, tmp);
+#pragma unroll
+      for (int t = 0; t < NFP; ++t) xs[(f * NFP + t) * S + l] = tmp[t];
+    }
+    __syncthreads();
+    // (c): GEMM on the matrix cores, (d): write + norm partials
+#pragma unroll
+    for (int t = 0; t < MTW; ++t) {
+      const int mt = w + t * NW;
+      if (mt >= MT) break;
+      v4 acc[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mt * 16 + Mfma<T>::row(lane, r);
+          acc[nt][r] = row < NLOC ? cc[(blk * NLOC + row) * kLanes + nt * 16 + li] : T(0);
+        }
+      }
+#pragma unroll
+      for (int ks = 0; ks < KT; ++ks) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const T b = xs[(ks * 4 + lk) * S + nt * 16 + li];
+          acc[nt] = Mfma<T>::mma(av[t][ks], b, acc[nt]);
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mt * 16 + Mfma<T>::row(lane, r);
+          if (row < NLOC) {
+            const int64_t o = (blk * NLOC + row) * kLanes + nt * 16 + li;
+            const T nv = acc[nt][r];
+            const double dd = (double)nv - (double)uin[o], wt = a.wnorm[row];
+            uout[o] = nv;
+            sd += wt * dd * dd;
+            su += wt * (double)nv * (double)nv;
+          }
+        }
+      }
+    }
+    // per-block partials (fixed order: waves, then lanes via the butterfly)
+    double bd = wave_sum(sd), bu = wave_sum(su);
+    sd = su = 0.0;
+    if (lane == 0) {
+      red[w] = bd;
+      red[NW + w] = bu;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int i = 0; i < NW; ++i) {
+        s0 += red[i];
+        s1 += red[NW + i];
+      }
+      a.partials[2 * blk] = s0;
+      a.partials[2 * blk + 1] = s1;
+    }
+  }
+}
+
+template <typename T, int PDE, int DIM, int P>
+hipError_t launch_mfma(const SweepArgs& a, hipStream_t s) {
+  // persistent: a few workgroups per CU loop over the 64-element blocks
+  const int64_t g = a.n_blk < 2048 ? a.n_blk : 2048;
+  hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 4>), dim3((unsigned)g), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int PDE, int DIM, int P, bool SHARED>
 hipError_t launch_one(int waves, const SweepArgs& a, hipStream_t s) {
+  if constexpr (SHARED) {
+    if (waves != 3) return launch_mfma<T, PDE, DIM, P>(a, s);  // waves == 3: vector-FMA reference variant
+  }
   dim3 grid((unsigned)a.n_blk);
   switch (waves) {
     case 1: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 1>), grid, dim3(64), 0, s, a); break;
