@@ -41,7 +41,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4a", "cfg4b"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4a", "cfg4b", "serve"])
+    ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
+    ap.add_argument("--rate", type=float, default=0.0, help="serve: arrival rate (0 = 0.8 x calibrated)")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle error and CPU baseline legs")
     ap.add_argument("--profile-pass", action="store_true",
@@ -126,15 +128,61 @@ def cpu_baseline(pr_full):
             "sample": f"oracle NumPy sweep, same recipe on {n}x{n} quads p={pr.p}, {k} sweeps after setup"}
 
 
+def serve(args):
+    """Serving mix: closed-loop calibration, then Poisson arrivals at 0.8 x the
+    calibrated throughput (unless --rate is given)."""
+    import torch
+
+    import workloads as w
+    from paper_1605_03228_amd.serving import Server
+    n = args.requests
+    probs = [w.serving_request(i) for i in range(n)]
+    srv = Server(hbm_budget_bytes=96 << 30, sweeps=16)
+    rate = args.rate
+    calib = None
+    if rate <= 0:
+        k = min(n, 200)
+        c = srv.serve([(i, 0.0, probs[i], 1e-8) for i in range(k)])
+        calib = {"requests": k, "wall_s": c["wall_s"], "throughput_req_s": c["throughput_req_s"]}
+        rate = 0.8 * c["throughput_req_s"]
+        torch.cuda.empty_cache()
+    t = w.arrival_times(n, rate, seed=12345)
+    out = srv.serve([(i, float(t[i]), probs[i], 1e-8) for i in range(n)])
+    recs = out["records"].values()
+    by = {}
+    for r in recs:
+        by.setdefault(r["path"], []).append(r["latency"])
+    line = {
+        "metric": "iHDG element-DOF updates/s/sweep (FP64 vs mixed) + p50/p99 solve latency",
+        "value": out["batched_dof_sweeps_per_s"],
+        "unit": "element-DOF updates/s (batched requests)",
+        "n_gpus": 1, "steps": n, "warmup": 0, "ms_per_step": 1e3 * out["wall_s"] / n,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64 (mixed)",
+        "data": "synthetic serving mix (seeded per request)",
+        "config": {"workload": f"serving mix: {n} requests, Poisson arrivals, PDE uniform over transport / "
+                               f"shallow water / conv.-diff., N log-uniform in [16, 256], p uniform 1..6, "
+                               f"tol 1e-8, mixed precision", "parallelism": "single GPU"},
+        "serving": {"rate_req_s": rate, "calibration": calib, "p50_latency_s": out["p50_latency_s"],
+                    "p99_latency_s": out["p99_latency_s"], "mean_latency_s": out["mean_latency_s"],
+                    "throughput_req_s": out["throughput_req_s"], "ok": out["ok"], "n": out["n"],
+                    "wall_s": out["wall_s"], "rounds": out["rounds"], "peak_hbm_bytes": out["peak_hbm_bytes"],
+                    "peak_active": out["peak_active"],
+                    "p50_by_path": {k: float(np.percentile(v, 50)) for k, v in by.items()},
+                    "count_by_path": {k: len(v) for k, v in by.items()}},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU only: the multi-GPU sharding of the sweep is a design, not code "
                                    "in this library", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "serve":
+        return serve(args)
     import torch
 
-    import workloads as w
     from paper_1605_03228_amd.problem_io import make_solver
 
     dev = "cuda"

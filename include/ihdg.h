@@ -144,7 +144,7 @@ typedef struct {
   ihdg_precision prec;
   int32_t check_every;     /* sweeps per convergence check (even; 0 = library default)        */
   int32_t max_iters;       /* sweep cap of ihdg_solve (0 = 100000)                            */
-  int32_t krylov_restart;  /* 0: plain iHDG; m > 0: GMRES(m) on (I - T)u = c, T the sweep     */
+  int32_t krylov_restart;  /* 0: plain iHDG; 0 < m <= 256: GMRES(m) on (I - T)u = c, T the sweep */
   double inner_rtol;       /* mixed: inner FP32 loop stops when its increment <= this x the
                               correction (0 = 1e-6)                                           */
   int32_t use_graph;       /* 1: replay sweep batches from a captured HIP graph               */
@@ -239,6 +239,40 @@ typedef struct {
   int32_t kernel_waves;     /* waves per workgroup used by the sweep kernel */
 } ihdg_stats;
 ihdg_status ihdg_get_stats(const ihdg_ctx* ctx, ihdg_stats* out);
+
+/*
+ * Batched solves (continuous batching).  A batch advances many contexts
+ * together: every round, each member performs up to `sweeps` sweeps of its own
+ * solve (the same FP64 iHDG or mixed defect-correction steps as ihdg_solve
+ * with check_every = sweeps), and members of the same shape (PDE, dimension,
+ * order, operator kind, precision) share one kernel launch per sweep whatever
+ * their mesh sizes.  A member's arithmetic does not depend on the other
+ * members, so its result is the same alone and in any mix.  Members may join
+ * (ihdg_batch_add) between rounds and leave when they finish; finished members
+ * are reported by ihdg_batch_poll and their contexts stay valid (the caller
+ * reads the solution and destroys them).  All batch work runs on the batch's
+ * stream; a member context must not be used elsewhere while it is in the batch.
+ *
+ * Device memory: ihdg_batch_footprint gives the bytes of `workspace` for at
+ * most max_members members whose 64-element blocks total at most max_blocks.
+ */
+typedef struct ihdg_batch ihdg_batch;
+typedef struct {
+  int64_t tag;        /* the caller's tag from ihdg_batch_add                      */
+  int32_t status;     /* IHDG_OK, IHDG_ERR_DIVERGED or IHDG_ERR_MAXITER            */
+  int32_t iters;      /* sweeps done (FP64 + FP32)                                */
+  double final_rel;   /* last relative increment (FP64) or FP64 defect (mixed)    */
+} ihdg_batch_result;
+ihdg_status ihdg_batch_footprint(int32_t max_members, int64_t max_blocks, size_t* bytes);
+ihdg_status ihdg_batch_create(int32_t max_members, int64_t max_blocks, void* workspace, size_t bytes, void* stream,
+                              ihdg_batch** out);
+/* Join the active set from the context's current iterate, to tolerance tol. */
+ihdg_status ihdg_batch_add(ihdg_batch* b, ihdg_ctx* ctx, double tol, int64_t tag);
+/* One round; n_active (nullable) receives the number of members still active. */
+ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active);
+/* Results of members that finished since the last poll (at most max_out). */
+ihdg_status ihdg_batch_poll(ihdg_batch* b, ihdg_batch_result* out, int32_t max_out, int32_t* n_out);
+void ihdg_batch_destroy(ihdg_batch* b);
 
 const char* ihdg_last_error(const ihdg_ctx* ctx);
 const char* ihdg_status_string(ihdg_status s);

@@ -40,6 +40,24 @@ class BoxMesh:
             stride *= self.n[a]
         return e
 
+    def origins(self):
+        """Lower corners of all elements, [n_el, dim] (lexicographic, x fastest)."""
+        idx = np.indices(tuple(reversed(self.n))).reshape(self.dim, -1)[::-1].T   # [n_el, dim], x fastest
+        return self.lo[None, :] + idx * self.h[None, :]
+
+    def neighbours(self):
+        """Neighbour across every local face, [n_el, 2*dim] (-1 on the boundary)."""
+        idx = np.indices(tuple(reversed(self.n))).reshape(self.dim, -1)[::-1].T
+        strides = np.cumprod([1] + list(self.n[:-1]))
+        e = np.arange(self.n_el)
+        out = np.full((self.n_el, 2 * self.dim), -1, dtype=np.int64)
+        for f in range(2 * self.dim):
+            a, s = divmod(f, 2)
+            step = 1 if s == 1 else -1
+            ok = (idx[:, a] + step >= 0) & (idx[:, a] + step < self.n[a])
+            out[:, f] = np.where(ok, e + step * strides[a], -1)
+        return out
+
     def el_origin(self, e):
         ijk = self.el_ijk(e)
         return np.array([self.lo[a] + ijk[a] * self.h[a] for a in range(self.dim)])
@@ -148,6 +166,12 @@ class TensorElement:
                     Mu[q, k] = np.prod([L[qm[t], km[t]] for t in range(dim - 1)]) if dim > 1 else 1.0
             self.face_q.append((Bf, Wf, rf, Mu))
         self.nfq = len(tq)
+
+    def all_volume_points(self, mesh):
+        return mesh.origins()[:, None, :] + (mesh.h / 2) * (self.rq + 1)[None]
+
+    def all_face_points(self, mesh, f):
+        return mesh.origins()[:, None, :] + (mesh.h / 2) * (self.face_q[f][2] + 1)[None]
 
     def volume_points(self, mesh, e):
         """Physical coordinates of the volume quadrature points of element e."""

@@ -40,34 +40,50 @@ class TransportOperators:
         J = mesh.jac()
         Dp = el.grad_phys(mesh)                      # [dim, nq, np]
         sig = prob.sigma_of_elements()
-        xq = np.array([el.volume_points(mesh, e) for e in range(ne)])   # [ne, nq, dim]
-        beta = prob.beta_at(xq)                                          # [ne, nq, dim]
-        divb = prob.div_beta_at(xq)                                      # [ne, nq]
-        fq = prob.forcing(xq, sig[:, None])[..., 0]                      # [ne, nq]
+        # constant coefficients: every element has the same local matrix
+        self.const = prob.beta is None and prob.div_beta is None and prob.sigma_el is None
+        xq = el.all_volume_points(mesh)                                   # [ne, nq, dim]
+        fq = prob.forcing(xq, sig[:, None])[..., 0]                       # [ne, nq]
         B, W = el.B, el.Wq
+        xa = xq[:1] if self.const else xq
+        sa = sig[:1] if self.const else sig
+        beta = prob.beta_at(xa)                                           # [na, nq, dim]
+        divb = prob.div_beta_at(xa)                                       # [na, nq]
         # volume: -(u, beta . grad v + (div beta) v) + sigma (u, v); rows = test i, cols = trial j
         bgrad = np.einsum("eqa,aqi->eqi", beta, Dp)                     # beta . grad l_i
         A = -np.einsum("q,qj,eqi->eij", W * J, B, bgrad + divb[:, :, None] * B[None])
-        A += np.einsum("e,q,qi,qj->eij", sig, W * J, B, B)
+        A += np.einsum("e,q,qi,qj->eij", sa, W * J, B, B)
         F = np.einsum("q,eq,qi->ei", W * J, fq, B)
         # faces
         self.bn = np.zeros((ne, nf, el.nfq))      # beta . n^- at face quadrature points
         self.g = np.zeros((ne, nf, el.nfq))
-        self.nbr = np.full((ne, nf), -1, dtype=np.int64)
+        self.nbr = mesh.neighbours()
         for f in range(nf):
             Bf, Wf, rf, _ = el.face_q[f]
             nvec = mesh.normal(f)
             Jf = mesh.face_jac(f)
-            xf = np.array([el.face_points(mesh, e, f) for e in range(ne)])  # [ne, nfq, dim]
+            xf = el.all_face_points(mesh, f)                                 # [ne, nfq, dim]
             bn = np.einsum("eqa,a->eq", prob.beta_at(xf), nvec)
             self.bn[:, f] = bn
             if prob.bdry is not None:
                 self.g[:, f] = prob.bdry(xf)[..., 0]
-            A += np.einsum("q,eq,qj,qi->eij", Wf * Jf, bn + np.abs(bn), Bf, Bf)
-            for e in range(ne):
-                self.nbr[e, f] = mesh.neighbour(e, f)
-        self.A, self.F = A, F
-        self.Ainv = np.linalg.inv(A)
+            ba = bn[:1] if self.const else bn
+            A += np.einsum("q,eq,qj,qi->eij", Wf * Jf, ba + np.abs(ba), Bf, Bf)
+        self.F = F
+        if self.const:
+            self.A0 = A[0]
+            self.Ainv0 = np.linalg.inv(A[0])
+            self.A = np.broadcast_to(self.A0, (ne,) + self.A0.shape)
+            self.Ainv = np.broadcast_to(self.Ainv0, (ne,) + self.A0.shape)
+        else:
+            self.A = A
+            self.Ainv = np.linalg.inv(A)
+
+    def solve_local(self, rhs):
+        """u_K = A_K^{-1} rhs_K for every element."""
+        if self.const:
+            return rhs @ self.Ainv0.T
+        return np.einsum("eij,ej->ei", self.Ainv, rhs)
 
     # ---------------------------------------------------------------------
     def weighted_trace(self, u):
@@ -107,7 +123,7 @@ class TransportOperators:
     def sweep(self, u):
         """One iHDG iteration: weighted trace from u^k, then all local solves."""
         w = self.weighted_trace(u)
-        return np.einsum("eij,ej->ei", self.Ainv, self.local_rhs(w))
+        return self.solve_local(self.local_rhs(w))
 
     def ihdg(self, tol=1e-13, max_iters=100000, u0=None, record=False):
         """Algorithm 1 from u^0 (default 0); stop on relative h-norm increment <= tol."""
@@ -209,7 +225,7 @@ class TransportOperators:
         kind = np.where(pos & neg, 0, np.where(neg, -1, 1))
         return kind
 
-    def downwind(self):
+    def downwind_loop(self):
         """Upwind DG solved element by element in flow order (block substitution).
 
         At the fixed point the weighted trace is |beta.n| times the upwind
@@ -256,6 +272,51 @@ class TransportOperators:
                     ext = self.g[e, f]
                 r += np.einsum("q,q,qi->i", Wf * Jf * np.maximum(-bn, 0), ext, Bf)
             u[e] = np.linalg.solve(M, r)
+        return u
+
+    def downwind(self):
+        """The same block substitution as downwind_loop, processed level by level.
+
+        Level of an element = 1 + the largest level of its inflow neighbours
+        (the flow layers of the proof of Theorem 1); all elements of a level
+        depend only on earlier levels, so each level is solved at once.
+        """
+        mesh, el = self.mesh, self.el
+        ne, nf = mesh.n_el, mesh.n_faces_el
+        kind = self.face_kind()
+        if (kind == 0).any():
+            raise ValueError("a face is partly inflow and partly outflow")
+        upw = np.where((kind == -1) & (self.nbr >= 0), self.nbr, -1)     # inflow neighbours
+        level = np.zeros(ne, dtype=np.int64)
+        done = np.zeros(ne, dtype=bool)
+        for it in range(ne + 1):
+            ready = ~done & np.all((upw < 0) | done[np.where(upw >= 0, upw, 0)], axis=1)
+            if not ready.any():
+                break
+            level[ready] = it
+            done |= ready
+        if not done.all():
+            raise ValueError("inflow graph has a cycle")
+        # M_K = A_K - O_K (own outflow part moved to the left)
+        O = 0.0
+        Bs = [el.face_q[f][0] for f in range(nf)]
+        Ws = [el.face_q[f][1] * mesh.face_jac(f) for f in range(nf)]
+        if self.const:
+            O = sum(np.einsum("q,q,qj,qi->ij", Ws[f], np.maximum(self.bn[0, f], 0), Bs[f], Bs[f]) for f in range(nf))
+            Minv = np.linalg.inv(self.A0 - O)
+        else:
+            O = sum(np.einsum("q,eq,qj,qi->eij", Ws[f], np.maximum(self.bn[:, f], 0), Bs[f], Bs[f]) for f in range(nf))
+            M = self.A - O
+        u = np.zeros((ne, el.np))
+        for L in range(level.max() + 1):
+            E = np.nonzero(level == L)[0]
+            r = self.F[E].copy()
+            for f in range(nf):
+                nb = self.nbr[E, f]
+                inner = nb >= 0
+                ext = np.where(inner[:, None], u[np.where(inner, nb, 0)] @ Bs[f ^ 1].T, self.g[E, f])
+                r += np.einsum("q,eq,qi->ei", Ws[f], np.maximum(-self.bn[E, f], 0) * ext, Bs[f])
+            u[E] = r @ Minv.T if self.const else np.linalg.solve(M[E], r[..., None])[..., 0]
         return u
 
     def iteration_matrix_diag_blocks(self):

@@ -1,6 +1,6 @@
 """MI355X iHDG library: Python binding of libihdg.so (see include/ihdg.h)."""
-from .binding import (CD, FP64, MIXED, SHALLOW_WATER, TRANSPORT, IhdgError, Solver, footprint,
+from .binding import (CD, FP64, MIXED, SHALLOW_WATER, TRANSPORT, Batch, IhdgError, Solver, footprint,
                       library_path, load, quadrature_points, sizes)
 
-__all__ = ["Solver", "IhdgError", "sizes", "quadrature_points", "footprint", "load", "library_path",
+__all__ = ["Solver", "Batch", "IhdgError", "sizes", "quadrature_points", "footprint", "load", "library_path",
            "TRANSPORT", "SHALLOW_WATER", "CD", "FP64", "MIXED"]

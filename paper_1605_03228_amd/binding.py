@@ -58,9 +58,15 @@ def library_path():
     return os.path.join(os.path.dirname(os.path.abspath(__file__)), "libihdg.so")
 
 
+class BatchResult(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("status", C.c_int32), ("iters", C.c_int32), ("final_rel", C.c_double)]
+
+
 EXPORTS = ["ihdg_sizes", "ihdg_quadrature_points", "ihdg_footprint", "ihdg_setup", "ihdg_sweep",
            "ihdg_solve", "ihdg_residual", "ihdg_get_solution", "ihdg_set_solution", "ihdg_set_stream",
-           "ihdg_get_stats", "ihdg_last_error", "ihdg_status_string", "ihdg_destroy"]
+           "ihdg_get_stats", "ihdg_last_error", "ihdg_status_string", "ihdg_destroy",
+           "ihdg_batch_footprint", "ihdg_batch_create", "ihdg_batch_add", "ihdg_batch_round",
+           "ihdg_batch_poll", "ihdg_batch_destroy"]
 
 
 def load():
@@ -92,8 +98,15 @@ def load():
     lib.ihdg_status_string.restype = C.c_char_p
     lib.ihdg_destroy.argtypes = [C.c_void_p]
     lib.ihdg_destroy.restype = None
+    lib.ihdg_batch_footprint.argtypes = [C.c_int32, C.c_int64, P(C.c_size_t)]
+    lib.ihdg_batch_create.argtypes = [C.c_int32, C.c_int64, C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_void_p)]
+    lib.ihdg_batch_add.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
+    lib.ihdg_batch_round.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
+    lib.ihdg_batch_poll.argtypes = [C.c_void_p, P(BatchResult), C.c_int32, P(C.c_int32)]
+    lib.ihdg_batch_destroy.argtypes = [C.c_void_p]
+    lib.ihdg_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("ihdg_last_error", "ihdg_status_string", "ihdg_destroy"):
+        if name not in ("ihdg_last_error", "ihdg_status_string", "ihdg_destroy", "ihdg_batch_destroy"):
             getattr(lib, name).restype = C.c_int
     _LIB = lib
     return lib
@@ -251,3 +264,58 @@ class Solver:
         s = Stats()
         _check(self.lib.ihdg_get_stats(self.ctx, C.byref(s)), self.ctx)
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+
+class Batch:
+    """Continuous batching of Solver contexts (ihdg_batch_*): members join between
+    rounds, every round advances each member by `sweeps` sweeps of its own solve
+    with one launch per group of same-shaped members, finished members are
+    reported by poll()."""
+
+    def __init__(self, max_members=256, max_blocks=1 << 20, device="cuda"):
+        lib = load()
+        self.lib, self.device = lib, torch.device(device)
+        nb = C.c_size_t()
+        _check(lib.ihdg_batch_footprint(max_members, max_blocks, C.byref(nb)))
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = C.c_void_p()
+        _check(lib.ihdg_batch_create(max_members, max_blocks, C.c_void_p(self.workspace.data_ptr()), nb.value,
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+        self.members = {}
+        self.max_members = max_members
+
+    def add(self, solver, tol, tag):
+        solver.stream.synchronize()
+        _check(self.lib.ihdg_batch_add(self.h, solver.ctx, tol, int(tag)))
+        self.members[int(tag)] = solver
+
+    def round(self, sweeps=16):
+        n = C.c_int32()
+        _check(self.lib.ihdg_batch_round(self.h, sweeps, C.byref(n)))
+        return n.value
+
+    def poll(self):
+        buf = (BatchResult * self.max_members)()
+        n = C.c_int32()
+        _check(self.lib.ihdg_batch_poll(self.h, buf, self.max_members, C.byref(n)))
+        self.stream.synchronize()
+        out = []
+        for i in range(n.value):
+            r = buf[i]
+            out.append({"tag": r.tag, "status": r.status, "iters": r.iters, "final_rel": r.final_rel,
+                        "solver": self.members.pop(r.tag, None)})
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.stream.synchronize()
+            self.lib.ihdg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -162,6 +162,8 @@ static bool decide_shared(ihdg_pde pde, const ihdg_coeffs* c, const ihdg_options
   return !c->beta_q && !c->bn_fq && !c->divbeta_q;
 }
 
+constexpr int kMaxRestart = 256;
+
 struct Layout {
   size_t off_u[2], off_c, off_tmp, off_G64, off_G32, off_Linv, off_P64, off_P32, off_d32, off_dl[2], off_fmap,
       off_w, off_part, off_norms, off_flags, off_kry, off_krypart, off_kryptr;
@@ -204,7 +206,7 @@ static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared
   L.off_flags = take(16 * 4);
   if (krylov > 0) {
     L.off_kry = take(nvec * 8 * (size_t)(krylov + 1));
-    L.off_krypart = take((size_t)m.n_blk * 16 * 8);
+    L.off_krypart = take((size_t)m.n_blk * 16 * 8 + (size_t)(krylov + 1) * 8);
     L.off_kryptr = take(16 * sizeof(double*));
   }
   L.total = o;
@@ -272,7 +274,7 @@ ihdg_status ihdg_footprint(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, c
   bool shared = decide_shared(pde, coeffs, opts);
   bool mixed = opts && opts->prec == IHDG_MIXED;
   int kry = opts ? opts->krylov_restart : 0;
-  if (kry < 0 || kry > 15) return IHDG_ERR_UNSUPPORTED;
+  if (kry < 0 || kry > kMaxRestart) return IHDG_ERR_UNSUPPORTED;
   Layout L = make_layout(mi, sz, shared, mixed, kry);
   *persistent_bytes = L.total;
   *scratch_bytes = L.scratch;
@@ -295,7 +297,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   if (o.check_every % 2) o.check_every += 1;
   if (o.max_iters <= 0) o.max_iters = 100000;
   if (o.inner_rtol <= 0) o.inner_rtol = 1e-6;
-  if (o.krylov_restart < 0 || o.krylov_restart > 15) return IHDG_ERR_UNSUPPORTED;
+  if (o.krylov_restart < 0 || o.krylov_restart > kMaxRestart) return IHDG_ERR_UNSUPPORTED;
   if (pde == IHDG_CONVDIFF && !(coeffs->kappa > 0)) return IHDG_ERR_ARG;
   if (pde == IHDG_SHALLOW_WATER && (!(coeffs->Phi > 0) || !(coeffs->mass_coef >= 0))) return IHDG_ERR_ARG;
   if (((uintptr_t)workspace & 255) || ((uintptr_t)scratch & 255)) return IHDG_ERR_ARG;
@@ -713,12 +715,13 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
   const int64_t N = c->nvec;
   double* V = c->kry;  // (m+1) vectors
   auto vec = [&](int j) { return V + (size_t)j * N; };
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 1);
   std::vector<double*> hptr(16);
   int64_t it = 0;
   double rel = INFINITY;
   double* u = c->u64[c->cur];
   double* tmp = c->tmp64;
+  double* hdev = c->kry_part + (size_t)c->mi.n_blk * 16;  // device copy of a Hessenberg column
   // <x, y_j>_h for the vectors y_0..y_{k-1} (device pointer list), k <= 16
   auto dots_with = [&](const double* x, const double* const* ys, int k, double* out) -> hipError_t {
     for (int j = 0; j < k; ++j) hptr[j] = const_cast<double*>(ys[j]);
@@ -731,10 +734,16 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(c->stream);
   };
+  // <x, V_j>_h for j < k, in chunks of 16
   auto dots = [&](const double* x, int k, double* out) -> hipError_t {
-    const double* ys[16];
-    for (int j = 0; j < k; ++j) ys[j] = vec(j);
-    return dots_with(x, ys, k, out);
+    for (int j0 = 0; j0 < k; j0 += 16) {
+      const double* ys[16];
+      int kk = std::min(16, k - j0);
+      for (int j = 0; j < kk; ++j) ys[j] = vec(j0 + j);
+      hipError_t e = dots_with(x, ys, kk, out + j0);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   };
   auto selfdot = [&](const double* x, double* out) -> hipError_t {
     const double* ys[1] = {x};
@@ -777,15 +786,13 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
     int j = 0;
     for (; j < m && it < c->opt.max_iters; ++j, ++it) {
       HIPCHK(c, apply(vec(j), vec(j + 1)));
-      // classical Gram-Schmidt, done twice for stability
+      // classical Gram-Schmidt, done twice for stability; each pass is one
+      // batch of dot products and one fused update w -= V h
       for (int pass = 0; pass < 2; ++pass) {
-        double h[16];
-        HIPCHK(c, dots(vec(j + 1), j + 1, h));
-        for (int i = 0; i <= j; ++i) {
-          if (pass == 0) H[i * m + j] = h[i];
-          else H[i * m + j] += h[i];
-          HIPCHK(c, launch_axpby(vec(j + 1), 1.0, vec(i), -h[i], N, c->stream));
-        }
+        HIPCHK(c, dots(vec(j + 1), j + 1, hcol.data()));
+        for (int i = 0; i <= j; ++i) H[i * m + j] = (pass == 0 ? 0.0 : H[i * m + j]) + hcol[i];
+        HIPCHK(c, hipMemcpyAsync(hdev, hcol.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, launch_multi_axpy(vec(j + 1), vec(0), hdev, j + 1, N, c->stream));
       }
       double nn;
       HIPCHK(c, selfdot(vec(j + 1), &nn));
@@ -825,3 +832,280 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
   }
   return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
 }
+
+// ---------------------------------------------------------------------------
+// batched solves
+// ---------------------------------------------------------------------------
+#include <map>
+#include <tuple>
+
+namespace {
+
+enum Mode { kModeF64 = 0, kModeDefect = 1, kModeF32 = 2 };
+
+struct BMember {
+  ihdg_ctx* c;
+  double tol;
+  int64_t tag;
+  int mode;
+  int64_t iters;
+  double best, ibest, prev, eta, rel;
+  int stall;
+};
+
+}  // namespace
+
+struct ihdg_batch {
+  hipStream_t stream;
+  int32_t max_members;
+  int64_t max_blocks;
+  BatchDesc* descs;  // device
+  int* owner;        // device
+  double* norms;     // device [2 * max_members]
+  std::vector<BMember> active;
+  std::vector<ihdg_batch_result> done;
+  std::string err;
+};
+
+static size_t batch_bytes(int32_t mm, int64_t mb, size_t* off_owner, size_t* off_norms) {
+  size_t o = 0;
+  o += al((size_t)mm * sizeof(BatchDesc));
+  *off_owner = o;
+  o += al((size_t)mb * sizeof(int));
+  *off_norms = o;
+  o += al((size_t)mm * 2 * sizeof(double));
+  return o;
+}
+
+static hipError_t launch_batched(const ihdg_ctx* c, bool fp32, const BatchDesc* d, const int* owner, int64_t nb,
+                                 int sidx, hipStream_t s) {
+  switch (c->pde) {
+    case IHDG_TRANSPORT:
+      return launch_sweep_batched_transport(c->mi.dim, c->mi.p, fp32, c->shared, c->waves, d, owner, nb, sidx, s);
+    case IHDG_SHALLOW_WATER:
+      return launch_sweep_batched_sw(c->mi.p, fp32, c->shared, c->waves, d, owner, nb, sidx, s);
+    case IHDG_CONVDIFF:
+      return launch_sweep_batched_cd(c->mi.p, fp32, c->shared, c->waves, d, owner, nb, sidx, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+extern "C" {
+
+ihdg_status ihdg_batch_footprint(int32_t max_members, int64_t max_blocks, size_t* bytes) {
+  if (max_members < 1 || max_blocks < 1 || !bytes) return IHDG_ERR_ARG;
+  size_t a, b;
+  *bytes = batch_bytes(max_members, max_blocks, &a, &b);
+  return IHDG_OK;
+}
+
+ihdg_status ihdg_batch_create(int32_t max_members, int64_t max_blocks, void* workspace, size_t bytes, void* stream,
+                              ihdg_batch** out) {
+  if (max_members < 1 || max_blocks < 1 || !workspace || !out) return IHDG_ERR_ARG;
+  if ((uintptr_t)workspace & 255) return IHDG_ERR_ARG;
+  size_t oo, on;
+  if (bytes < batch_bytes(max_members, max_blocks, &oo, &on)) return IHDG_ERR_NOMEM;
+  ihdg_batch* b = new ihdg_batch();
+  b->stream = (hipStream_t)stream;
+  b->max_members = max_members;
+  b->max_blocks = max_blocks;
+  b->descs = (BatchDesc*)workspace;
+  b->owner = (int*)((char*)workspace + oo);
+  b->norms = (double*)((char*)workspace + on);
+  *out = b;
+  return IHDG_OK;
+}
+
+void ihdg_batch_destroy(ihdg_batch* b) { delete b; }
+
+ihdg_status ihdg_batch_add(ihdg_batch* b, ihdg_ctx* c, double tol, int64_t tag) {
+  if (!b || !c || !(tol > 0)) return IHDG_ERR_ARG;
+  if ((int32_t)b->active.size() >= b->max_members) return IHDG_ERR_NOMEM;
+  int64_t blocks = c->mi.n_blk;
+  for (const BMember& m : b->active) {
+    if (m.c == c) return IHDG_ERR_ARG;
+    blocks += m.c->mi.n_blk;
+  }
+  if (blocks > b->max_blocks) return IHDG_ERR_NOMEM;
+  if (c->opt.krylov_restart > 0) return IHDG_ERR_UNSUPPORTED;
+  BMember m{};
+  m.c = c;
+  m.tol = tol;
+  m.tag = tag;
+  m.mode = c->mixed ? kModeDefect : kModeF64;
+  m.best = m.ibest = m.prev = m.rel = INFINITY;
+  c->stats.fp64_sweeps = c->stats.fp32_sweeps = 0;
+  c->stats.outer_steps = c->stats.krylov_iters = 0;
+  b->active.push_back(m);
+  return IHDG_OK;
+}
+
+ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
+  if (!b || sweeps < 1) return IHDG_ERR_ARG;
+  hipStream_t st = b->stream;
+  const int S = sweeps;
+  if (b->active.empty()) {
+    if (n_active) *n_active = 0;
+    return IHDG_OK;
+  }
+  // group members by kernel shape and mode
+  typedef std::tuple<int, int, int, int, int, int, int> Key;  // pde, dim, p, shared, fp32, single, waves
+  std::map<Key, std::vector<int>> groups;
+  for (int i = 0; i < (int)b->active.size(); ++i) {
+    const BMember& m = b->active[i];
+    const ihdg_ctx* c = m.c;
+    Key k{(int)c->pde, c->mi.dim, c->mi.p, c->shared ? 1 : 0, m.mode == kModeF32 ? 1 : 0,
+          m.mode == kModeDefect ? 1 : 0, c->waves};
+    groups[k].push_back(i);
+  }
+  std::vector<BatchDesc> hd;
+  std::vector<int> ho;
+  std::vector<int> order;  // desc slot -> active index
+  struct G {
+    Key k;
+    int d0;
+    int64_t o0, nb;
+    const ihdg_ctx* rep;
+  };
+  std::vector<G> gl;
+  for (auto& kv : groups) {
+    G g{kv.first, (int)hd.size(), (int64_t)ho.size(), 0, b->active[kv.second[0]].c};
+    int local = 0;
+    for (int i : kv.second) {
+      const BMember& m = b->active[i];
+      const ihdg_ctx* c = m.c;
+      BatchDesc d{};
+      if (m.mode == kModeF64) {
+        d.u[0] = c->u64[0];
+        d.u[1] = c->u64[1];
+        d.parity0 = c->cur;
+        d.c = c->c64;
+        d.G = c->G64;
+        d.P = c->P64;
+      } else if (m.mode == kModeDefect) {
+        d.u[0] = c->u64[c->cur];
+        d.u[1] = c->tmp64;
+        d.parity0 = 0;
+        d.c = c->c64;
+        d.G = c->G64;
+        d.P = c->P64;
+      } else {
+        d.u[0] = c->dl32[0];
+        d.u[1] = c->dl32[1];
+        d.parity0 = c->cur32;
+        d.c = c->d32;
+        d.G = c->G32;
+        d.P = c->P32;
+      }
+      d.fmap = c->fmap;
+      d.wnorm = c->wnorm;
+      d.partials = c->partials;
+      d.n_blk = c->mi.n_blk;
+      d.blk0 = g.nb;
+      d.sqrt_phi = c->sqrt_phi;
+      for (int64_t k = 0; k < c->mi.n_blk; ++k) ho.push_back(local);
+      g.nb += c->mi.n_blk;
+      hd.push_back(d);
+      order.push_back(i);
+      ++local;
+    }
+    gl.push_back(g);
+  }
+  if ((int64_t)ho.size() > b->max_blocks) return IHDG_ERR_NOMEM;
+  if (hipMemcpyAsync(b->descs, hd.data(), hd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(b->owner, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
+    return IHDG_ERR_HIP;
+  for (int s = 0; s < S; ++s) {
+    for (const G& g : gl) {
+      const bool single = std::get<5>(g.k) != 0;
+      if (single && s > 0) continue;
+      const bool fp32 = std::get<4>(g.k) != 0;
+      if (launch_batched(g.rep, fp32, b->descs + g.d0, b->owner + g.o0, g.nb, s, st) != hipSuccess) return IHDG_ERR_HIP;
+    }
+  }
+  if (launch_reduce_batched(b->descs, (int)hd.size(), b->norms, st) != hipSuccess) return IHDG_ERR_HIP;
+  std::vector<double> hn(2 * hd.size());
+  if (hipMemcpyAsync(hn.data(), b->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return IHDG_ERR_HIP;
+  // state machines
+  std::vector<char> finished(b->active.size(), 0);
+  for (size_t slot = 0; slot < order.size(); ++slot) {
+    BMember& m = b->active[order[slot]];
+    ihdg_ctx* c = m.c;
+    const double inc = std::sqrt(hn[2 * slot]), nrm = std::sqrt(hn[2 * slot + 1]);
+    int status = -1;
+    if (m.mode == kModeF64) {
+      m.iters += S;
+      c->stats.fp64_sweeps += S;
+      if (S % 2) c->cur ^= 1;
+      m.rel = nrm > 0 ? inc / nrm : inc;
+      if (!std::isfinite(inc)) status = IHDG_ERR_DIVERGED;
+      else if (inc <= m.tol * nrm || inc == 0.0) status = IHDG_OK;
+      else if (inc > 1e3 * (m.best = std::min(m.best, inc))) status = IHDG_ERR_DIVERGED;
+      else if (m.iters >= c->opt.max_iters) status = IHDG_ERR_MAXITER;
+    } else if (m.mode == kModeDefect) {
+      m.iters += 1;
+      c->stats.fp64_sweeps += 1;
+      c->stats.outer_steps += 1;
+      m.rel = nrm > 0 ? inc / nrm : inc;
+      if (!std::isfinite(inc)) status = IHDG_ERR_DIVERGED;
+      else if (inc <= m.tol * nrm || inc == 0.0) status = IHDG_OK;
+      else if (inc > 1e3 * (m.best = std::min(m.best, inc))) status = IHDG_ERR_DIVERGED;
+      else if (m.iters >= c->opt.max_iters) status = IHDG_ERR_MAXITER;
+      else {
+        m.eta = std::max(c->opt.inner_rtol, std::min(0.1, 0.3 * m.tol * nrm / inc));
+        if (launch_diff_to_f32(c->tmp64, c->u64[c->cur], c->d32, c->nvec, st) != hipSuccess ||
+            launch_fill_zero_f32(c->dl32[0], c->nvec, st) != hipSuccess ||
+            launch_fill_zero_f32(c->dl32[1], c->nvec, st) != hipSuccess)
+          return IHDG_ERR_HIP;
+        c->cur32 = 0;
+        m.mode = kModeF32;
+        m.ibest = m.prev = INFINITY;
+        m.stall = 0;
+      }
+    } else {
+      m.iters += S;
+      c->stats.fp32_sweeps += S;
+      if (S % 2) c->cur32 ^= 1;
+      bool stop = false;
+      if (!std::isfinite(inc)) status = IHDG_ERR_DIVERGED;
+      else if (inc <= m.eta * nrm || inc == 0.0) stop = true;
+      else if (inc > 1e3 * (m.ibest = std::min(m.ibest, inc))) status = IHDG_ERR_DIVERGED;
+      else {
+        if (inc > 0.9 * m.prev && inc < 1e-4 * nrm) {
+          if (++m.stall >= 2) stop = true;
+        } else {
+          m.stall = 0;
+        }
+        m.prev = inc;
+      }
+      if (status < 0 && m.iters >= c->opt.max_iters) status = IHDG_ERR_MAXITER;
+      if (stop && status < 0) {
+        if (launch_add_f32_to_f64(c->u64[c->cur], c->dl32[c->cur32], c->nvec, st) != hipSuccess) return IHDG_ERR_HIP;
+        m.mode = kModeDefect;
+      }
+    }
+    if (status >= 0) {
+      b->done.push_back(ihdg_batch_result{m.tag, status, (int32_t)m.iters, m.rel});
+      finished[order[slot]] = 1;
+    }
+  }
+  std::vector<BMember> keep;
+  for (size_t i = 0; i < b->active.size(); ++i)
+    if (!finished[i]) keep.push_back(b->active[i]);
+  b->active.swap(keep);
+  if (n_active) *n_active = (int32_t)b->active.size();
+  return IHDG_OK;
+}
+
+ihdg_status ihdg_batch_poll(ihdg_batch* b, ihdg_batch_result* out, int32_t max_out, int32_t* n_out) {
+  if (!b || !n_out || (max_out > 0 && !out)) return IHDG_ERR_ARG;
+  int32_t n = std::min<int32_t>(max_out, (int32_t)b->done.size());
+  for (int32_t i = 0; i < n; ++i) out[i] = b->done[i];
+  b->done.erase(b->done.begin(), b->done.begin() + n);
+  *n_out = n;
+  return IHDG_OK;
+}
+
+}  // extern "C"

@@ -57,6 +57,39 @@ struct SweepArgs {
   double sqrt_phi;      // shallow water sqrt(Phi)
 };
 
+// One member of a batched sweep: its buffers, its first block in the bucket's
+// block list, and the parity of its iterate at sweep 0 of the launch sequence.
+struct BatchDesc {
+  const void* u[2];  // ping-pong iterate (or correction) buffers
+  const void* c;     // affine part (c_K, or the FP32 defect)
+  const void* G;
+  const void* P;
+  const int* fmap;
+  const double* wnorm;
+  double* partials;
+  int64_t n_blk;
+  int64_t blk0;
+  double sqrt_phi;
+  int parity0;
+  int pad_;
+};
+
+__host__ __device__ inline SweepArgs batch_args(const BatchDesc& d, int s) {
+  SweepArgs a{};
+  const int p = (d.parity0 + s) & 1;
+  a.uin = d.u[p];
+  a.uout = (void*)d.u[p ^ 1];
+  a.c = d.c;
+  a.G = d.G;
+  a.P = d.P;
+  a.fmap = d.fmap;
+  a.wnorm = d.wnorm;
+  a.partials = d.partials;
+  a.n_blk = d.n_blk;
+  a.sqrt_phi = d.sqrt_phi;
+  return a;
+}
+
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 hipError_t launch_shared_c(const SetupArgs& a, hipStream_t s);
 hipError_t launch_maps(const SetupArgs& a, int* fmap, hipStream_t s);
@@ -70,6 +103,13 @@ hipError_t launch_sweep_transport(int dim, int p, bool fp32, bool shared, int wa
 hipError_t launch_sweep_sw(int p, bool fp32, bool shared, int waves, const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_cd(int p, bool fp32, bool shared, int waves, const SweepArgs& a, hipStream_t s);
 
+hipError_t launch_sweep_batched_transport(int dim, int p, bool fp32, bool shared, int waves, const BatchDesc* d,
+                                          const int* owner, int64_t nb, int sidx, hipStream_t s);
+hipError_t launch_sweep_batched_sw(int p, bool fp32, bool shared, int waves, const BatchDesc* d, const int* owner,
+                                   int64_t nb, int sidx, hipStream_t s);
+hipError_t launch_sweep_batched_cd(int p, bool fp32, bool shared, int waves, const BatchDesc* d, const int* owner,
+                                   int64_t nb, int sidx, hipStream_t s);
+
 // Small vector kernels (vector_ops.hip).
 hipError_t launch_reduce_partials(const double* partials, int64_t n_blk, double* out2, hipStream_t s);
 hipError_t launch_diff_to_f32(const double* a, const double* b, float* out, int64_t n, hipStream_t s);
@@ -79,6 +119,9 @@ hipError_t launch_fill_zero_f64(double* x, int64_t n, hipStream_t s);
 hipError_t launch_to_user(const double* u_il, double* u_user, int64_t n_el, int n_loc, hipStream_t s);
 hipError_t launch_from_user(const double* u_user, double* u_il, int64_t n_el, int n_loc, hipStream_t s);
 hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s);
+hipError_t launch_multi_axpy(double* w, const double* V, const double* h, int k, int64_t n, hipStream_t s);
+// norms[2 i + j] = sum over member i's blocks of its partials (fixed order)
+hipError_t launch_reduce_batched(const BatchDesc* descs, int n, double* norms, hipStream_t s);
 hipError_t launch_dots(const double* x, const double* const* ys, int k, const double* w, int n_loc,
                        int64_t n_blk, double* partial, double* out, hipStream_t s);
 

@@ -134,17 +134,13 @@ __device__ inline void face_step_to(const SweepArgs& a, int64_t blk, int f, int 
 // for that occupancy and no more, so it can keep a whole operator row in
 // flight instead of serialising the loads.
 template <typename T, int PDE, int DIM, int P, bool SHARED, int NW>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW < 4 ? 4 : NW, 8)))
-void k_sweep(SweepArgs a) {
+__device__ __forceinline__ void sweep_block(const SweepArgs& a, int64_t blk, T* xs, double* red) {
   constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
   constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
   constexpr int RPT = (NLOC + NW - 1) / NW;                      // rows per thread
   constexpr bool XREG = NIN * sizeof(T) <= 32 * sizeof(double);  // keep x_K in registers
-  __shared__ T xs[NIN * kLanes];
-  __shared__ double red[2 * NW];
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t blk = blockIdx.x;
   const T* __restrict__ uin = (const T*)a.uin;
   T* __restrict__ uout = (T*)a.uout;
   const T* __restrict__ cc = (const T*)a.c;
@@ -213,6 +209,30 @@ void k_sweep(SweepArgs a) {
   }
 }
 
+template <typename T, int PDE, int DIM, int P, bool SHARED, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW < 4 ? 4 : NW, 8)))
+void k_sweep(SweepArgs a) {
+  constexpr int NIN = 2 * DIM * ipow(P + 1, DIM - 1);
+  __shared__ T xs[NIN * kLanes];
+  __shared__ double red[2 * NW];
+  sweep_block<T, PDE, DIM, P, SHARED, NW>(a, blockIdx.x, xs, red);
+}
+
+// Batched sweep over the members of one bucket (same PDE, dimension, order,
+// operator kind and precision, any mesh size): global block b belongs to member
+// owner[b]; sweep index s selects each member's ping-pong buffers.
+template <typename T, int PDE, int DIM, int P, bool SHARED, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW < 4 ? 4 : NW, 8)))
+void k_sweep_batched(const BatchDesc* __restrict__ descs, const int* __restrict__ owner, int s) {
+  constexpr int NIN = 2 * DIM * ipow(P + 1, DIM - 1);
+  __shared__ T xs[NIN * kLanes];
+  __shared__ double red[2 * NW];
+  const int m = owner[blockIdx.x];
+  const BatchDesc& d = descs[m];
+  SweepArgs a = batch_args(d, s);
+  sweep_block<T, PDE, DIM, P, SHARED, NW>(a, (int64_t)blockIdx.x - d.blk0, xs, red);
+}
+
 // ---------------------------------------------------------------------------
 // Shared operator: the local solve of a block of 64 elements is one GEMM,
 // U (n_loc x 64) = C + G (n_loc x n_in) X (n_in x 64), on the matrix cores.
@@ -241,104 +261,141 @@ struct Mfma<double> {
 };
 
 template <typename T, int PDE, int DIM, int P, int NW>
-__global__ __launch_bounds__(64 * NW) void k_sweep_mfma(SweepArgs a) {
-  constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
-  constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
-  constexpr int MT = (NLOC + 15) / 16, KT = (NIN + 3) / 4;
-  constexpr int MTW = (MT + NW - 1) / NW;  // row tiles per wave
-  constexpr int S = kLanes + Mfma<T>::kPad; // LDS row stride of X
+struct MfmaShape {
+  static constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
+  static constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
+  static constexpr int MT = (NLOC + 15) / 16, KT = (NIN + 3) / 4;
+  static constexpr int MTW = (MT + NW - 1) / NW;    // row tiles per wave
+  static constexpr int S = kLanes + Mfma<T>::kPad;  // LDS row stride of X
+};
+
+// this wave's slice of G as MFMA A operands
+template <typename T, int PDE, int DIM, int P, int NW>
+__device__ __forceinline__ void mfma_load_a(const SweepArgs& a, T (&av)[MfmaShape<T, PDE, DIM, P, NW>::MTW][MfmaShape<T, PDE, DIM, P, NW>::KT]) {
+  typedef MfmaShape<T, PDE, DIM, P, NW> Sh;
+  const T* __restrict__ G = (const T*)a.G;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < Sh::MTW; ++t) {
+    const int mt = w + t * NW;
+#pragma unroll
+    for (int ks = 0; ks < Sh::KT; ++ks) {
+      const int r = mt * 16 + li, k = ks * 4 + lk;
+      av[t][ks] = (mt < Sh::MT && r < Sh::NLOC && k < Sh::NIN) ? G[r * Sh::NIN + k] : T(0);
+    }
+  }
+}
+
+// one 64-element block: face step into LDS, GEMM on the matrix cores, write +
+// norm partials.  The padding rows of xs (k >= n_in) must be zero.
+template <typename T, int PDE, int DIM, int P, int NW>
+__device__ __forceinline__ void mfma_block(const SweepArgs& a, int64_t blk,
+                                           const T (&av)[MfmaShape<T, PDE, DIM, P, NW>::MTW][MfmaShape<T, PDE, DIM, P, NW>::KT],
+                                           T* xs, double* red) {
+  typedef MfmaShape<T, PDE, DIM, P, NW> Sh;
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T xs[KT * 4 * S];
-  __shared__ double red[2 * NW];
+  constexpr int NFP = Sh::NFP, NLOC = Sh::NLOC, S = Sh::S;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const T* __restrict__ G = (const T*)a.G;
   const T* __restrict__ uin = (const T*)a.uin;
   T* __restrict__ uout = (T*)a.uout;
   const T* __restrict__ cc = (const T*)a.c;
   const int li = lane & 15, lk = lane >> 4;
-
-  // A operand, resident for the whole kernel
-  T av[MTW][KT];
+  // (a) + (b): face step writes x[k][element] into LDS (row stride S)
+  for (int fl = tid; fl < Sh::NF * kLanes; fl += 64 * NW) {
+    T tmp[NFP];
+    const int f = fl >> 6, l = fl & 63;
+    face_step_to<T, PDE, DIM, P>(a, blk, f, l, tmp);
 #pragma unroll
-  for (int t = 0; t < MTW; ++t) {
-    const int mt = w + t * NW;
-#pragma unroll
-    for (int ks = 0; ks < KT; ++ks) {
-      const int r = mt * 16 + li, k = ks * 4 + lk;
-      av[t][ks] = (mt < MT && r < NLOC && k < NIN) ? G[r * NIN + k] : T(0);
-    }
+    for (int t = 0; t < NFP; ++t) xs[(f * NFP + t) * S + l] = tmp[t];
   }
-  // zero padding rows of X once (k >= NIN)
-  for (int i = tid; i < (KT * 4 - NIN) * S; i += 64 * NW) xs[NIN * S + i] = T(0);
-
+  __syncthreads();
+  // (c): GEMM on the matrix cores, (d): write + norm partials
   double sd = 0.0, su = 0.0;
-  for (int64_t blk = blockIdx.x; blk < a.n_blk; blk += gridDim.x) {
-    // (a) + (b): face step writes x[k][element] into LDS (row stride S)
-    for (int fl = tid; fl < NF * kLanes; fl += 64 * NW) {
-      T tmp[NFP];
-      const int f = fl >> 6, l = fl & 63;
-      face_step_to<T, PDE, DIM, P>(a, blk, f, l, tmp);
 #pragma unroll
-      for (int t = 0; t < NFP; ++t) xs[(f * NFP + t) * S + l] = tmp[t];
+  for (int t = 0; t < Sh::MTW; ++t) {
+    const int mt = w + t * NW;
+    if (mt >= Sh::MT) break;
+    v4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + Mfma<T>::row(lane, r);
+        acc[nt][r] = row < NLOC ? cc[(blk * NLOC + row) * kLanes + nt * 16 + li] : T(0);
+      }
     }
-    __syncthreads();
-    // (c): GEMM on the matrix cores, (d): write + norm partials
 #pragma unroll
-    for (int t = 0; t < MTW; ++t) {
-      const int mt = w + t * NW;
-      if (mt >= MT) break;
-      v4 acc[4];
+    for (int ks = 0; ks < Sh::KT; ++ks) {
 #pragma unroll
       for (int nt = 0; nt < 4; ++nt) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = mt * 16 + Mfma<T>::row(lane, r);
-          acc[nt][r] = row < NLOC ? cc[(blk * NLOC + row) * kLanes + nt * 16 + li] : T(0);
-        }
-      }
-#pragma unroll
-      for (int ks = 0; ks < KT; ++ks) {
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          const T b = xs[(ks * 4 + lk) * S + nt * 16 + li];
-          acc[nt] = Mfma<T>::mma(av[t][ks], b, acc[nt]);
-        }
-      }
-#pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = mt * 16 + Mfma<T>::row(lane, r);
-          if (row < NLOC) {
-            const int64_t o = (blk * NLOC + row) * kLanes + nt * 16 + li;
-            const T nv = acc[nt][r];
-            const double dd = (double)nv - (double)uin[o], wt = a.wnorm[row];
-            uout[o] = nv;
-            sd += wt * dd * dd;
-            su += wt * (double)nv * (double)nv;
-          }
-        }
+        const T b = xs[(ks * 4 + lk) * S + nt * 16 + li];
+        acc[nt] = Mfma<T>::mma(av[t][ks], b, acc[nt]);
       }
     }
-    // per-block partials (fixed order: waves, then lanes via the butterfly)
-    double bd = wave_sum(sd), bu = wave_sum(su);
-    sd = su = 0.0;
-    if (lane == 0) {
-      red[w] = bd;
-      red[NW + w] = bu;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double s0 = 0.0, s1 = 0.0;
-      for (int i = 0; i < NW; ++i) {
-        s0 += red[i];
-        s1 += red[NW + i];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + Mfma<T>::row(lane, r);
+        if (row < NLOC) {
+          const int64_t o = (blk * NLOC + row) * kLanes + nt * 16 + li;
+          const T nv = acc[nt][r];
+          const double dd = (double)nv - (double)uin[o], wt = a.wnorm[row];
+          uout[o] = nv;
+          sd += wt * dd * dd;
+          su += wt * (double)nv * (double)nv;
+        }
       }
-      a.partials[2 * blk] = s0;
-      a.partials[2 * blk + 1] = s1;
     }
   }
+  // per-block partials (fixed order: waves, then lanes via the butterfly)
+  const double bd = wave_sum(sd), bu = wave_sum(su);
+  if (lane == 0) {
+    red[w] = bd;
+    red[NW + w] = bu;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < NW; ++i) {
+      s0 += red[i];
+      s1 += red[NW + i];
+    }
+    a.partials[2 * blk] = s0;
+    a.partials[2 * blk + 1] = s1;
+  }
+}
+
+template <typename T, int PDE, int DIM, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_mfma(SweepArgs a) {
+  typedef MfmaShape<T, PDE, DIM, P, NW> Sh;
+  __shared__ T xs[Sh::KT * 4 * Sh::S];
+  __shared__ double red[2 * NW];
+  T av[Sh::MTW][Sh::KT];
+  mfma_load_a<T, PDE, DIM, P, NW>(a, av);
+  for (int i = threadIdx.x; i < (Sh::KT * 4 - Sh::NIN) * Sh::S; i += 64 * NW) xs[Sh::NIN * Sh::S + i] = T(0);
+  for (int64_t blk = blockIdx.x; blk < a.n_blk; blk += gridDim.x) {
+    mfma_block<T, PDE, DIM, P, NW>(a, blk, av, xs, red);
+    __syncthreads();  // xs and red are reused by the next block
+  }
+}
+
+template <typename T, int PDE, int DIM, int P, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_mfma_batched(const BatchDesc* __restrict__ descs,
+                                                                const int* __restrict__ owner, int s) {
+  typedef MfmaShape<T, PDE, DIM, P, NW> Sh;
+  __shared__ T xs[Sh::KT * 4 * Sh::S];
+  __shared__ double red[2 * NW];
+  const int m = owner[blockIdx.x];
+  const BatchDesc& d = descs[m];
+  const SweepArgs a = batch_args(d, s);
+  T av[Sh::MTW][Sh::KT];
+  mfma_load_a<T, PDE, DIM, P, NW>(a, av);
+  for (int i = threadIdx.x; i < (Sh::KT * 4 - Sh::NIN) * Sh::S; i += 64 * NW) xs[Sh::NIN * Sh::S + i] = T(0);
+  mfma_block<T, PDE, DIM, P, NW>(a, (int64_t)blockIdx.x - d.blk0, av, xs, red);
 }
 
 template <typename T, int PDE, int DIM, int P>
@@ -362,6 +419,36 @@ hipError_t launch_one(int waves, const SweepArgs& a, hipStream_t s) {
     default: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 4>), grid, dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
+}
+
+template <typename T, int PDE, int DIM, int P, bool SHARED>
+hipError_t launch_one_batched(int waves, const BatchDesc* descs, const int* owner, int64_t nblocks, int sidx,
+                              hipStream_t s) {
+  dim3 grid((unsigned)nblocks);
+  if constexpr (SHARED) {
+    if (waves != 3) {
+      hipLaunchKernelGGL((k_sweep_mfma_batched<T, PDE, DIM, P, 4>), grid, dim3(256), 0, s, descs, owner, sidx);
+      return hipGetLastError();
+    }
+  }
+  switch (waves) {
+    case 1: hipLaunchKernelGGL((k_sweep_batched<T, PDE, DIM, P, SHARED, 1>), grid, dim3(64), 0, s, descs, owner, sidx); break;
+    case 2: hipLaunchKernelGGL((k_sweep_batched<T, PDE, DIM, P, SHARED, 2>), grid, dim3(128), 0, s, descs, owner, sidx); break;
+    case 8: hipLaunchKernelGGL((k_sweep_batched<T, PDE, DIM, P, SHARED, 8>), grid, dim3(512), 0, s, descs, owner, sidx); break;
+    default: hipLaunchKernelGGL((k_sweep_batched<T, PDE, DIM, P, SHARED, 4>), grid, dim3(256), 0, s, descs, owner, sidx); break;
+  }
+  return hipGetLastError();
+}
+
+template <int PDE, int DIM, int P>
+hipError_t launch_variants_batched(bool fp32, bool shared, int waves, const BatchDesc* descs, const int* owner,
+                                   int64_t nblocks, int sidx, hipStream_t s) {
+  if (fp32) {
+    return shared ? launch_one_batched<float, PDE, DIM, P, true>(waves, descs, owner, nblocks, sidx, s)
+                  : launch_one_batched<float, PDE, DIM, P, false>(waves, descs, owner, nblocks, sidx, s);
+  }
+  return shared ? launch_one_batched<double, PDE, DIM, P, true>(waves, descs, owner, nblocks, sidx, s)
+                : launch_one_batched<double, PDE, DIM, P, false>(waves, descs, owner, nblocks, sidx, s);
 }
 
 template <int PDE, int DIM, int P>

@@ -111,6 +111,41 @@ __global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ p
   }
 }
 
+// w -= sum_j h[j] V_j, V_j = V + j * n (contiguous basis vectors), h on the device
+__global__ void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, const double* __restrict__ h, int k,
+                             int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    double s = w[i];
+    for (int j = 0; j < k; ++j) s -= h[j] * V[(int64_t)j * n + i];
+    w[i] = s;
+  }
+}
+
+// one workgroup per batch member: the same fixed-order reduction as k_reduce
+__global__ __launch_bounds__(256) void k_reduce_batched(const BatchDesc* __restrict__ descs, double* norms) {
+  __shared__ double s0[256], s1[256];
+  const BatchDesc& d = descs[blockIdx.x];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < d.n_blk; i += 256) {
+    a += d.partials[2 * i];
+    b += d.partials[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    norms[2 * blockIdx.x] = s0[0];
+    norms[2 * blockIdx.x + 1] = s1[0];
+  }
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 16384) b = 16384;
@@ -148,6 +183,15 @@ hipError_t launch_from_user(const double* u_user, double* u_il, int64_t n_el, in
 }
 hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(256), 0, s, y, a, x, b, n);
+  return hipGetLastError();
+}
+hipError_t launch_multi_axpy(double* w, const double* V, const double* h, int k, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n)), dim3(256), 0, s, w, V, h, k, n);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_batched(const BatchDesc* descs, int n, double* norms, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)n), dim3(256), 0, s, descs, norms);
   return hipGetLastError();
 }
 hipError_t launch_dots(const double* x, const double* const* ys, int k, const double* w, int n_loc, int64_t n_blk,

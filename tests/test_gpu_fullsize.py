@@ -1,0 +1,83 @@
+"""GPU parity at the benchmark sizes, in the launch configuration bench.py uses.
+
+Each configuration is solved on the GPU from u^0 = 0 and compared element by
+element (relative h-norm over the whole mesh) with the oracle's own solution of
+the same discrete problem: downwind block substitution for transport, the
+assembled HDG trace system for shallow water and convection-diffusion.  FP64
+runs to a relative increment of 1e-12 must agree to 1e-10; mixed-precision
+runs to a relative FP64 defect of 1e-10 must agree to 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle.convdiff import CDOperators
+from oracle.norms import h_norm
+from oracle.shallow_water import SWOperators
+from oracle.transport import TransportOperators
+
+pytestmark = pytest.mark.gpu
+
+_REF = {}
+
+
+def reference(name, make):
+    if name not in _REF:
+        pr = make()
+        o = {"transport": TransportOperators, "sw": SWOperators, "cd": CDOperators}[pr.pde](pr)
+        ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
+        _REF[name] = (pr, o, ref)
+    return _REF[name]
+
+
+def run(pr, tol, **kw):
+    from paper_1605_03228_amd.problem_io import make_solver
+    print(f"[gpu] {pr.name} tol={tol} {kw}", flush=True)
+    s = make_solver(pr, **kw)
+    res = s.solve(tol)
+    u = s.get_solution().reshape(pr.n_el, -1).cpu().numpy()
+    s.close()
+    torch.cuda.empty_cache()
+    return res, u
+
+
+CONFIGS = [("cfg2", lambda: w.config2(seed=0)), ("cfg3", lambda: w.config3(seed=0)),
+           ("cfg4a", lambda: w.config4a(seed=0)), ("cfg4b_1e-4", lambda: w.config4b(eps=1e-4))]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("name,make", CONFIGS, ids=[c[0] for c in CONFIGS])
+def test_fullsize_fp64(name, make):
+    pr, o, ref = reference(name, make)
+    res, u = run(pr, 1e-12)
+    assert res["status"] == 0, res
+    err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
+    print(f"{name} fp64: {res['iters']} sweeps, rel err {err:.3e}")
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("name,make", CONFIGS, ids=[c[0] for c in CONFIGS])
+def test_fullsize_mixed(name, make):
+    pr, o, ref = reference(name, make)
+    res, u = run(pr, 1e-10, prec=1)
+    assert res["status"] == 0, res
+    err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
+    print(f"{name} mixed: {res['fp32_sweeps']} fp32 + {res['fp64_sweeps']} fp64 sweeps, rel err {err:.3e}")
+    assert err < 1e-8
+
+
+def test_fullsize_cd_eps1e2_gmres():
+    """eps = 1e-2 is outside the plain iteration's convergence region (Tables 3-4);
+    GMRES(100) with the sweep as operator reaches the HDG solution."""
+    pr, o, ref = reference("cfg4b_1e-2", lambda: w.config4b(eps=1e-2))
+    res, u = run(pr, 1e-12, krylov_restart=100, max_iters=20000)
+    assert res["status"] == 0, res
+    err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
+    print(f"cfg4b eps=1e-2 gmres: {res['krylov_iters']} iterations, rel err {err:.3e}")
+    assert err < 1e-9

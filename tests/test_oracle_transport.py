@@ -62,6 +62,13 @@ def test_ihdg_equals_direct_equals_downwind(make):
     assert rel(o, u, ud) < 1e-11
 
 
+@pytest.mark.parametrize("make", [lambda: w.config2(n=9, p=3), lambda: w.config3(n=4, p=2),
+                                  lambda: w.transport_e2(3, 2), lambda: w.transport_affine_beta((5, 4), 2)])
+def test_downwind_by_levels_equals_element_loop(make):
+    o = TransportOperators(make())
+    assert np.abs(o.downwind() - o.downwind_loop()).max() < 1e-13
+
+
 @pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_contraction_factor_theorem1(p):
     """Spectral radius of the iteration <= 2^{-1/2} (Theorem 1); exactly 1/2 when

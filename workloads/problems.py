@@ -377,3 +377,30 @@ def transport_e2(n, p):
     return Problem(pde="transport", dim=3, n=(n, n, n), p=p, beta=beta, sigma_const=0.0,
                    forcing=f, bdry=lambda x, xp=np: _u3(x, xp)[..., None],
                    exact=lambda x, xp=np: _u3(x, xp)[..., None], name=f"e2_transport_{n}^3_p{p}")
+
+
+def serving_request(i):
+    """Request i of the serving mix (seeded by its index): PDE uniform over
+    {transport, shallow water, conv.-diff.}, N = round(exp(U[ln 16, ln 256])),
+    p uniform in 1..6; coefficients as in the single-problem configs (transport:
+    variable beta and per-element sigma; shallow water: f0 ~ U[0, 1], one
+    Crank-Nicolson step; conv.-diff.: eps uniform over {1e-2, 1e-4})."""
+    rng = np.random.default_rng(i)
+    pde = ("transport", "sw", "cd")[int(rng.integers(3))]
+    n = int(round(float(np.exp(rng.uniform(np.log(16.0), np.log(256.0))))))
+    p = int(rng.integers(1, 7))
+    if pde == "transport":
+        pr = config2(seed=1000 + i, n=n, p=p)
+    elif pde == "sw":
+        pr = config4a(seed=1000 + i, n=n, p=p)
+    else:
+        eps = (1e-2, 1e-4)[int(rng.integers(2))]
+        pr = config4b(eps=eps, n=n, p=p)
+    pr.meta["request"] = i
+    return pr
+
+
+def arrival_times(n, rate, seed=12345):
+    """Poisson arrivals: cumulative sums of exponential gaps with mean 1/rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
