@@ -142,14 +142,20 @@ typedef struct {
 
 typedef struct {
   ihdg_precision prec;
-  int32_t check_every;     /* sweeps per convergence check (even; 0 = library default)        */
+  int32_t check_every;     /* sweeps per convergence check (0 = library default, 16)           */
   int32_t max_iters;       /* sweep cap of ihdg_solve (0 = 100000)                            */
   int32_t krylov_restart;  /* 0: plain iHDG; 0 < m <= 256: GMRES(m) on (I - T)u = c, T the sweep */
   double inner_rtol;       /* mixed: inner FP32 loop stops when its increment <= this x the
                               correction (0 = 1e-6)                                           */
   int32_t use_graph;       /* 1: replay sweep batches from a captured HIP graph               */
   int32_t force_per_element; /* 1: per-element operators even where one could be shared      */
-  int32_t block_waves;     /* waves per workgroup of the sweep kernel (0 = autotuned/default)  */
+  int32_t block_waves;     /* launch shape of the sweep kernel: 0 = autotuned at setup (cached per
+                              shape), 1/2/4/8 = waves per 64-element block, 3 = vector-FMA shared */
+  int32_t time_stepping;   /* 1: keep what ihdg_time_step needs (shared operators only)               */
+  int32_t transport_flux;  /* transport only: 0 = upwind HDG flux (eq. RiemannFluxBoth with |A| = |beta.n|),
+                              1 = the NPC flux analysed after Theorem 1 (eq. Ntaub): tau = 0 on outflow,
+                              |beta.n| on inflow, so the iteration terminates after as many sweeps as the
+                              mesh has flow layers (Theorem 2); same fixed point                        */
 } ihdg_options;
 
 /* Discretisation sizes for (mesh, order, pde).  No device work. */
@@ -167,6 +173,13 @@ ihdg_status ihdg_sizes(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, ihdg_
  */
 ihdg_status ihdg_quadrature_points(const ihdg_mesh* mesh, int32_t order, double* xq_dev,
                                    double* xfq_dev, void* stream);
+
+/*
+ * Coordinates of the GLL nodes of every element, x_dev [n_el][np][dim]
+ * (nodes lexicographic, x fastest): where a nodal initial state or warm start
+ * for ihdg_set_solution is evaluated.  `stream` is a hipStream_t.
+ */
+ihdg_status ihdg_node_points(const ihdg_mesh* mesh, int32_t order, double* x_dev, void* stream);
 
 /*
  * Device memory the caller must provide to ihdg_setup for these arguments:
@@ -224,6 +237,23 @@ ihdg_status ihdg_residual(ihdg_ctx* ctx, double* defect_norm);
  * Stream-ordered; no synchronisation. */
 ihdg_status ihdg_get_solution(ihdg_ctx* ctx, double* u_dev);
 ihdg_status ihdg_set_solution(ihdg_ctx* ctx, const double* u_dev);
+
+/*
+ * Time marching (the time-dependent remarks of Sections 3 and 4 and the
+ * shallow-water experiment of Section 5): turn the current iterate u^n into the
+ * right-hand side of the next implicit step, keeping u^n as the warm start of
+ * the next ihdg_solve.  The context's operator is the implicit one,
+ * A = mass_coef * M_Phi + S (M_Phi: the mass matrix, times Phi on the
+ * shallow-water velocity fields; S: the spatial HDG operator), with forcing
+ * part c_f = A^{-1} F set at setup.
+ *   scheme 0, backward Euler:  c <- c_f + H u^n
+ *   scheme 1, Crank-Nicolson written as (2/dt) M (u^{n+1} - u^n) + L u^{n+1} + L u^n = 2 f,
+ *             i.e. mass_coef = 2/dt:  c <- c_f + 2 H u^n - u^n + G x(u^n)
+ * with H = mass_coef A^{-1} M_Phi and G x(u^n) the trace part of one sweep of
+ * u^n.  Requires opts.time_stepping = 1 and a shared operator
+ * (IHDG_ERR_UNSUPPORTED otherwise).  Stream-ordered.
+ */
+ihdg_status ihdg_time_step(ihdg_ctx* ctx, int32_t scheme);
 
 /* Change the stream all later work of ctx is ordered on (a hipStream_t). */
 ihdg_status ihdg_set_stream(ihdg_ctx* ctx, void* stream);

@@ -55,6 +55,10 @@ class SWOperators:
             A[:npn, 2 * npn:] += Phi * nv[1] * Mf
         self.A = A
         self.Ainv = np.linalg.inv(A)
+        # mass matrix of the time derivative: (phi, w1), (Phi u, w2), (Phi v, w3)
+        Z = np.zeros_like(Mm)
+        self.Mt = np.block([[Mm, Z, Z], [Z, Phi * Mm, Z], [Z, Z, Phi * Mm]])
+        self.mass_coef = c
         xq = np.array([el.volume_points(mesh, e) for e in range(ne)])
         Fq = prob.forcing(xq)                                      # [ne, nq, 3]
         self.F = np.einsum("q,eqm,qi->emi", W * J, Fq, B).reshape(ne, 3 * npn)
@@ -181,6 +185,30 @@ class SWOperators:
                     r += Cf[f] @ lam[k * nfp:(k + 1) * nfp]
             U[e] = Abinv[e] @ r
         return U
+
+    def spatial(self, U):
+        """The HDG spatial operator applied to U with its own trace: L(U) = S U - E(trace(U)),
+        where S is the local matrix without the mass term and E the trace terms."""
+        ne = self.mesh.n_el
+        S = self.A - self.mass_coef * self.Mt
+        Ue = U.reshape(ne, -1)
+        return Ue @ S.T - (self.local_rhs(self.trace(Ue)) - self.F)
+
+    def cn_step_rhs(self, Un):
+        """Crank-Nicolson, (2/dt) M (U^{n+1} - U^n) + L(U^{n+1}) + L(U^n) = 2 f, with the
+        implicit operator (a/dt) M + L of this object (a = 2): the forcing of the step is
+        F + (2/dt) M U^n - L(U^n)."""
+        return self.F + self.mass_coef * (Un @ self.Mt.T) - self.spatial(Un)
+
+    def solve_with_forcing(self, F, direct=True, u0=None, tol=1e-13):
+        F0 = self.F
+        self.F = F
+        try:
+            if direct:
+                return self.direct_hdg()
+            return self.ihdg(tol=tol, u0=u0)
+        finally:
+            self.F = F0
 
     def nodal(self, fn):
         return np.array([fn(self.el.node_points(self.mesh, e)).T.reshape(-1) for e in range(self.mesh.n_el)])

@@ -29,10 +29,18 @@ from .norms import h_norm
 
 
 class TransportOperators:
-    """Per-element local matrices and face data of the upwind HDG scheme."""
+    """Per-element local matrices and face data of the upwind HDG scheme.
 
-    def __init__(self, prob, mesh=None, el=None):
+    flux="npc" selects the flux of Nguyen, Peraire and Cockburn that the paper
+    analyses after Theorem 1 (eq. Ntaub): stabilisation
+    tau = |beta.n| (1 + sgn(beta.n))/2 - beta.n, trace
+    uhat^k = ({{tau u^k}} + {{beta.n u^k}}) / {{tau}}, and the iteration applied
+    to uhat itself, without the |beta.n| weighting (Theorem 2: exact after J
+    iterations)."""
+
+    def __init__(self, prob, mesh=None, el=None, flux="upwind"):
         self.prob = prob
+        self.flux = flux
         self.mesh = mesh or BoxMesh(prob.n, prob.lo, prob.hi)
         self.el = el or TensorElement(prob.dim, prob.p)
         mesh, el = self.mesh, self.el
@@ -68,7 +76,8 @@ class TransportOperators:
             if prob.bdry is not None:
                 self.g[:, f] = prob.bdry(xf)[..., 0]
             ba = bn[:1] if self.const else bn
-            A += np.einsum("q,eq,qj,qi->eij", Wf * Jf, ba + np.abs(ba), Bf, Bf)
+            # <beta.n u + tau u, v>: upwind tau = |beta.n|; NPC tau as above
+            A += np.einsum("q,eq,qj,qi->eij", Wf * Jf, ba + self.tau(ba), Bf, Bf)
         self.F = F
         if self.const:
             self.A0 = A[0]
@@ -78,6 +87,12 @@ class TransportOperators:
         else:
             self.A = A
             self.Ainv = np.linalg.inv(A)
+
+    def tau(self, bn):
+        """Stabilisation on a face from the element's side, bn = beta . n."""
+        if self.flux == "npc":
+            return np.abs(bn) * (1.0 + np.sign(bn)) / 2.0 - bn
+        return np.abs(bn)
 
     def solve_local(self, rhs):
         """u_K = A_K^{-1} rhs_K for every element."""
@@ -104,10 +119,20 @@ class TransportOperators:
             inner = nb >= 0
             up = u[np.where(inner, nb, 0)] @ Bo.T
             bn_p = -bn_m
-            # interior: {{beta.n u}} + |beta.n| {{u}}
-            w_int = 0.5 * (bn_m * um + bn_p * up) + np.abs(bn_m) * 0.5 * (um + up)
-            # boundary: |beta.n| g on inflow points, |beta.n| u (own) on outflow points
-            w_bdy = np.where(bn_m < 0, np.abs(bn_m) * self.g[:, f], np.abs(bn_m) * um)
+            if self.flux == "npc":
+                # tau uhat with uhat = ({{tau u}} + {{beta.n u}}) / {{tau}}; tau^- uhat is what the
+                # local equation needs (it multiplies the test function)
+                tm, tp = self.tau(bn_m), self.tau(bn_p)
+                avg_tau = 0.5 * (tm + tp)
+                with np.errstate(divide="ignore", invalid="ignore"):
+                    uhat = np.where(avg_tau > 0, (0.5 * (tm * um + tp * up) + 0.5 * (bn_m * um + bn_p * up)) / avg_tau, 0.0)
+                w_int = tm * uhat
+                w_bdy = np.where(bn_m < 0, tm * self.g[:, f], 0.0)
+            else:
+                # interior: {{beta.n u}} + |beta.n| {{u}}
+                w_int = 0.5 * (bn_m * um + bn_p * up) + np.abs(bn_m) * 0.5 * (um + up)
+                # boundary: |beta.n| g on inflow points, |beta.n| u (own) on outflow points
+                w_bdy = np.where(bn_m < 0, np.abs(bn_m) * self.g[:, f], np.abs(bn_m) * um)
             w[:, f] = np.where(inner[:, None], w_int, w_bdy)
         return w
 
@@ -283,20 +308,7 @@ class TransportOperators:
         """
         mesh, el = self.mesh, self.el
         ne, nf = mesh.n_el, mesh.n_faces_el
-        kind = self.face_kind()
-        if (kind == 0).any():
-            raise ValueError("a face is partly inflow and partly outflow")
-        upw = np.where((kind == -1) & (self.nbr >= 0), self.nbr, -1)     # inflow neighbours
-        level = np.zeros(ne, dtype=np.int64)
-        done = np.zeros(ne, dtype=bool)
-        for it in range(ne + 1):
-            ready = ~done & np.all((upw < 0) | done[np.where(upw >= 0, upw, 0)], axis=1)
-            if not ready.any():
-                break
-            level[ready] = it
-            done |= ready
-        if not done.all():
-            raise ValueError("inflow graph has a cycle")
+        level = self.flow_levels()
         # M_K = A_K - O_K (own outflow part moved to the left)
         O = 0.0
         Bs = [el.face_q[f][0] for f in range(nf)]
@@ -318,6 +330,27 @@ class TransportOperators:
                 r += np.einsum("q,eq,qi->ei", Ws[f], np.maximum(-self.bn[E, f], 0) * ext, Bs[f])
             u[E] = r @ Minv.T if self.const else np.linalg.solve(M[E], r[..., None])[..., 0]
         return u
+
+    def flow_levels(self):
+        """Level of every element in the inflow graph: 0 for elements whose inflow
+        faces are all on the boundary, else 1 + the largest level of their inflow
+        neighbours (the sets K^i of the proof of Theorem 1)."""
+        ne = self.mesh.n_el
+        kind = self.face_kind()
+        if (kind == 0).any():
+            raise ValueError("a face is partly inflow and partly outflow")
+        upw = np.where((kind == -1) & (self.nbr >= 0), self.nbr, -1)     # inflow neighbours
+        level = np.zeros(ne, dtype=np.int64)
+        done = np.zeros(ne, dtype=bool)
+        for it in range(ne + 1):
+            ready = ~done & np.all((upw < 0) | done[np.where(upw >= 0, upw, 0)], axis=1)
+            if not ready.any():
+                break
+            level[ready] = it
+            done |= ready
+        if not done.all():
+            raise ValueError("inflow graph has a cycle")
+        return level
 
     def iteration_matrix_diag_blocks(self):
         """T_KK = A_K^{-1} O_K: the self-coupling of an element through its lagged outflow trace.

@@ -43,7 +43,8 @@ class Coeffs(C.Structure):
 class Options(C.Structure):
     _fields_ = [("prec", C.c_int), ("check_every", C.c_int32), ("max_iters", C.c_int32),
                 ("krylov_restart", C.c_int32), ("inner_rtol", C.c_double), ("use_graph", C.c_int32),
-                ("force_per_element", C.c_int32), ("block_waves", C.c_int32)]
+                ("force_per_element", C.c_int32), ("block_waves", C.c_int32), ("time_stepping", C.c_int32),
+                ("transport_flux", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -66,7 +67,7 @@ EXPORTS = ["ihdg_sizes", "ihdg_quadrature_points", "ihdg_footprint", "ihdg_setup
            "ihdg_solve", "ihdg_residual", "ihdg_get_solution", "ihdg_set_solution", "ihdg_set_stream",
            "ihdg_get_stats", "ihdg_last_error", "ihdg_status_string", "ihdg_destroy",
            "ihdg_batch_footprint", "ihdg_batch_create", "ihdg_batch_add", "ihdg_batch_round",
-           "ihdg_batch_poll", "ihdg_batch_destroy"]
+           "ihdg_batch_poll", "ihdg_batch_destroy", "ihdg_time_step", "ihdg_node_points"]
 
 
 def load():
@@ -103,6 +104,8 @@ def load():
     lib.ihdg_batch_add.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
     lib.ihdg_batch_round.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.ihdg_batch_poll.argtypes = [C.c_void_p, P(BatchResult), C.c_int32, P(C.c_int32)]
+    lib.ihdg_time_step.argtypes = [C.c_void_p, C.c_int32]
+    lib.ihdg_node_points.argtypes = [P(Mesh), C.c_int32, C.c_void_p, C.c_void_p]
     lib.ihdg_batch_destroy.argtypes = [C.c_void_p]
     lib.ihdg_batch_destroy.restype = None
     for name in EXPORTS:
@@ -149,6 +152,15 @@ def quadrature_points(n, order, lo=None, hi=None, device="cuda"):
     return xq, xfq
 
 
+def node_points(n, order, lo=None, hi=None, device="cuda"):
+    """GLL node coordinates of every element, [n_el, np, dim] FP64 on the device."""
+    s = sizes(n, order, TRANSPORT, lo, hi)
+    x = torch.empty((s["n_el"], s["np"], len(n)), dtype=torch.float64, device=device)
+    _check(load().ihdg_node_points(C.byref(_mesh(n, lo, hi)), order, C.c_void_p(x.data_ptr()), _stream(device)))
+    torch.cuda.current_stream(device).synchronize()
+    return x
+
+
 def _ptr(t):
     if t is None:
         return None
@@ -169,7 +181,7 @@ def _coeffs(c):
 
 
 def _options(prec=FP64, check_every=16, max_iters=0, krylov_restart=0, inner_rtol=0.0, use_graph=True,
-             force_per_element=False, block_waves=0):
+             force_per_element=False, block_waves=0, flux="upwind", time_stepping=False):
     o = Options()
     o.prec = prec
     o.check_every = check_every
@@ -179,6 +191,8 @@ def _options(prec=FP64, check_every=16, max_iters=0, krylov_restart=0, inner_rto
     o.use_graph = 1 if use_graph else 0
     o.force_per_element = 1 if force_per_element else 0
     o.block_waves = block_waves
+    o.transport_flux = {"upwind": 0, "npc": 1}[flux]
+    o.time_stepping = 1 if time_stepping else 0
     return o
 
 
@@ -246,6 +260,11 @@ class Solver:
         out = (C.c_double * 2)()
         _check(self.lib.ihdg_residual(self.ctx, out), self.ctx)
         return out[0], out[1]
+
+    def time_step(self, scheme="cn"):
+        """Form the next implicit step's right-hand side from the current iterate
+        (which stays as the warm start): scheme "be" or "cn"."""
+        _check(self.lib.ihdg_time_step(self.ctx, {"be": 0, "cn": 1}[scheme]), self.ctx)
 
     def get_solution(self):
         u = torch.empty((self.sz["n_el"], self.sz["m"], self.sz["np"]), dtype=torch.float64, device=self.device)

@@ -16,6 +16,7 @@ namespace ihdg {
 constexpr int kMaxP = 6;
 constexpr int kMax1 = 8;   // >= p + 2 for p <= kMaxP
 constexpr int kLanes = 64; // elements per interleave block (one wavefront)
+constexpr int kXcds = 8;   // accelerator complex dies of the MI355X (each with its own L2)
 
 enum Pde : int { kTransport = 0, kShallowWater = 1, kConvDiff = 2 };
 

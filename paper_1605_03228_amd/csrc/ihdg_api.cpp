@@ -40,12 +40,15 @@ struct ihdg_ctx {
   double* wnorm;
   double* partials;
   double* norms;     // device scratch for reductions (64 doubles)
+  double* Ht;        // time stepping: H = mass_coef L^{-1} M_Phi (shared), or null
+  double* cf;        // time stepping: the forcing part of c, A^{-1} F
   double* kry;       // Krylov basis, (m+1) vectors (or null)
   double* kry_part;  // partials for the Krylov dot products
   double** kry_ptrs; // device array of pointers for the dots kernel
   int cur;
   int cur32;
-  int waves;
+  int waves;    // launch shape of the FP64 sweep kernel (waves per block; 3 = vector-FMA shared variant)
+  int waves32;  // same for the FP32 correction sweeps
   double sqrt_phi;
   hipGraphExec_t g64[2];
   hipGraphExec_t g32[2];
@@ -165,6 +168,7 @@ static bool decide_shared(ihdg_pde pde, const ihdg_coeffs* c, const ihdg_options
 constexpr int kMaxRestart = 256;
 
 struct Layout {
+  size_t off_Ht, off_cf;
   size_t off_u[2], off_c, off_tmp, off_G64, off_G32, off_Linv, off_P64, off_P32, off_d32, off_dl[2], off_fmap,
       off_w, off_part, off_norms, off_flags, off_kry, off_krypart, off_kryptr;
   size_t total;
@@ -174,7 +178,8 @@ struct Layout {
 
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared, bool mixed, int krylov) {
+static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared, bool mixed, int krylov,
+                          bool timestep = false) {
   Layout L{};
   const size_t nvec = (size_t)m.n_blk * kLanes * sz.n_loc;
   const size_t nG = shared ? (size_t)sz.n_loc * sz.n_in : nvec * sz.n_in;
@@ -204,6 +209,10 @@ static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared
   L.off_part = take((size_t)m.n_blk * 2 * 8);
   L.off_norms = take(64 * 8);
   L.off_flags = take(16 * 4);
+  if (timestep && shared) {
+    L.off_Ht = take((size_t)sz.n_loc * sz.n_loc * 8);
+    L.off_cf = take(nvec * 8);
+  }
   if (krylov > 0) {
     L.off_kry = take(nvec * 8 * (size_t)(krylov + 1));
     L.off_krypart = take((size_t)m.n_blk * 16 * 8 + (size_t)(krylov + 1) * 8);
@@ -218,6 +227,9 @@ static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared
   L.scratch = al(per * chunk);
   return L;
 }
+
+static hipError_t autotune(ihdg_ctx* c);
+static hipError_t one_sweep(ihdg_ctx* c, bool fp32, const void* uin, void* uout, const void* cvec);
 
 // ---------------------------------------------------------------------------
 // ABI
@@ -263,6 +275,18 @@ ihdg_status ihdg_quadrature_points(const ihdg_mesh* mesh, int32_t order, double*
   return IHDG_OK;
 }
 
+ihdg_status ihdg_node_points(const ihdg_mesh* mesh, int32_t order, double* x_dev, void* stream) {
+  std::string why;
+  MeshInfo mi;
+  ihdg_sizes_t sz{};
+  ihdg_status s = make_sizes(mesh, order, IHDG_TRANSPORT, &mi, &sz, &why);
+  if (s != IHDG_OK) return s;
+  if (!x_dev) return IHDG_ERR_ARG;
+  RefTab rt = make_reftab(order, mi.dim);
+  if (launch_node_points(mi, rt, x_dev, (hipStream_t)stream) != hipSuccess) return IHDG_ERR_HIP;
+  return IHDG_OK;
+}
+
 ihdg_status ihdg_footprint(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
                            const ihdg_options* opts, size_t* persistent_bytes, size_t* scratch_bytes) {
   std::string why;
@@ -275,7 +299,7 @@ ihdg_status ihdg_footprint(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, c
   bool mixed = opts && opts->prec == IHDG_MIXED;
   int kry = opts ? opts->krylov_restart : 0;
   if (kry < 0 || kry > kMaxRestart) return IHDG_ERR_UNSUPPORTED;
-  Layout L = make_layout(mi, sz, shared, mixed, kry);
+  Layout L = make_layout(mi, sz, shared, mixed, kry, opts && opts->time_stepping);
   *persistent_bytes = L.total;
   *scratch_bytes = L.scratch;
   return IHDG_OK;
@@ -293,8 +317,8 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   ihdg_options o{};
   if (opts) o = *opts;
   if (o.prec != IHDG_FP64 && o.prec != IHDG_MIXED) return IHDG_ERR_ARG;
+  if (o.transport_flux != 0 && o.transport_flux != 1) return IHDG_ERR_ARG;
   if (o.check_every <= 0) o.check_every = 16;
-  if (o.check_every % 2) o.check_every += 1;
   if (o.max_iters <= 0) o.max_iters = 100000;
   if (o.inner_rtol <= 0) o.inner_rtol = 1e-6;
   if (o.krylov_restart < 0 || o.krylov_restart > kMaxRestart) return IHDG_ERR_UNSUPPORTED;
@@ -303,7 +327,8 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   if (((uintptr_t)workspace & 255) || ((uintptr_t)scratch & 255)) return IHDG_ERR_ARG;
   const bool shared = decide_shared(pde, coeffs, &o);
   const bool mixed = o.prec == IHDG_MIXED;
-  Layout L = make_layout(mi, sz, shared, mixed, o.krylov_restart);
+  if (o.time_stepping && !shared) return IHDG_ERR_UNSUPPORTED;
+  Layout L = make_layout(mi, sz, shared, mixed, o.krylov_restart, o.time_stepping != 0);
   if (workspace_bytes < L.total) return IHDG_ERR_NOMEM;
   const size_t ncol = shared ? (size_t)(2 * sz.n_loc + sz.n_in) : (size_t)(sz.n_loc + sz.n_in + 1);
   const size_t per = (size_t)sz.n_loc * ncol * 8;
@@ -339,6 +364,8 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   c->partials = (double*)(ws + L.off_part);
   c->norms = (double*)(ws + L.off_norms);
   int* flags = (int*)(ws + L.off_flags);
+  c->Ht = (o.time_stepping && shared) ? (double*)(ws + L.off_Ht) : nullptr;
+  c->cf = (o.time_stepping && shared) ? (double*)(ws + L.off_cf) : nullptr;
   c->kry = o.krylov_restart > 0 ? (double*)(ws + L.off_kry) : nullptr;
   c->kry_part = o.krylov_restart > 0 ? (double*)(ws + L.off_krypart) : nullptr;
   c->kry_ptrs = o.krylov_restart > 0 ? (double**)(ws + L.off_kryptr) : nullptr;
@@ -346,6 +373,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   c->cur32 = 0;
   c->sqrt_phi = pde == IHDG_SHALLOW_WATER ? std::sqrt(coeffs->Phi) : 0.0;
   c->waves = o.block_waves > 0 ? o.block_waves : 4;
+  c->waves32 = c->waves;
   c->g64[0] = c->g64[1] = c->g32[0] = c->g32[1] = nullptr;
   c->g64_n = c->g32_n = 0;
   memset(&c->stats, 0, sizeof(c->stats));
@@ -390,6 +418,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   a.cf.gamma = coeffs->gamma;
   a.cf.mass_coef = coeffs->mass_coef;
   a.pde = (int)pde;
+  a.flux = (pde == IHDG_TRANSPORT && o.transport_flux == 1) ? 1 : 0;
   a.m = sz.m;
   a.n_loc = sz.n_loc;
   a.n_in = sz.n_in;
@@ -424,6 +453,11 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
       if (launch_setup(a, st) != hipSuccess) return bail(IHDG_ERR_HIP, "setup");
     }
   }
+  if (c->Ht) {
+    if (launch_time_operator(a, c->Ht, st) != hipSuccess ||
+        hipMemcpyAsync(c->cf, c->c64, c->nvec * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return bail(IHDG_ERR_HIP, "time operator");
+  }
   int hflags[2] = {0, 0};
   if (hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
@@ -438,6 +472,13 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
     ihdg_destroy(c);
     return IHDG_ERR_SINGULAR_LOCAL;
   }
+  if (o.block_waves == 0) {
+    if (autotune(c) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+      ihdg_destroy(c);
+      return IHDG_ERR_HIP;
+    }
+  }
+  c->stats.kernel_waves = c->waves;
   *out = c;
   return IHDG_OK;
 }
@@ -445,8 +486,8 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
 void ihdg_destroy(ihdg_ctx* c) {
   if (!c) return;
   for (int k = 0; k < 2; ++k) {
-    if (c->g64[k]) hipGraphExecDestroy(c->g64[k]);
-    if (c->g32[k]) hipGraphExecDestroy(c->g32[k]);
+    if (c->g64[k]) (void)hipGraphExecDestroy(c->g64[k]);
+    if (c->g32[k]) (void)hipGraphExecDestroy(c->g32[k]);
   }
   delete c;
 }
@@ -494,7 +535,89 @@ static hipError_t one_sweep(ihdg_ctx* c, bool fp32, const void* uin, void* uout,
   a.partials = c->partials;
   a.n_blk = c->mi.n_blk;
   a.sqrt_phi = c->sqrt_phi;
-  return ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, c->waves, a, c->stream);
+  return ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, fp32 ? c->waves32 : c->waves, a,
+                            c->stream);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time the candidate launch shapes of the sweep kernel on scratch
+// buffers (the iterate is not touched) and keep the fastest.  Results are
+// cached per (PDE, dimension, order, operator kind, precision, size class).
+// ---------------------------------------------------------------------------
+#include <mutex>
+#include <map>
+#include <tuple>
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int, int, int, int>, int> g_tuned;
+
+static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
+  const int64_t nb = c->mi.n_blk;
+  int cls = 0;
+  while ((int64_t)1 << (cls + 1) <= nb) ++cls;
+  const auto key = std::make_tuple((int)c->pde, c->mi.dim, c->mi.p, c->shared ? 1 : 0, fp32 ? 1 : 0, cls);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) {
+      *best = it->second;
+      return hipSuccess;
+    }
+  }
+  std::vector<int> cand = c->shared ? std::vector<int>{4, 8, 3} : std::vector<int>{1, 2, 4, 8};
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) return e;
+  const void* uin = fp32 ? (const void*)c->dl32[0] : (const void*)c->u64[c->cur];
+  void* uout = fp32 ? (void*)c->dl32[1] : (void*)c->tmp64;
+  const void* cv = fp32 ? (const void*)c->d32 : (const void*)c->c64;
+  float bestt = 1e30f;
+  int bw = cand[0];
+  const int reps = nb >= 256 ? 5 : 20;
+  for (int w : cand) {
+    SweepArgs a{};
+    a.uin = uin;
+    a.uout = uout;
+    a.c = cv;
+    a.G = fp32 ? (const void*)c->G32 : (const void*)c->G64;
+    a.P = fp32 ? (const void*)c->P32 : (const void*)c->P64;
+    a.fmap = c->fmap;
+    a.wnorm = c->wnorm;
+    a.partials = c->partials;
+    a.n_blk = nb;
+    a.sqrt_phi = c->sqrt_phi;
+    for (int i = 0; i < 2; ++i)
+      if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, a, c->stream)) != hipSuccess)
+        return e;
+    hipEventRecord(e0, c->stream);
+    for (int i = 0; i < reps; ++i)
+      if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, a, c->stream)) != hipSuccess)
+        return e;
+    hipEventRecord(e1, c->stream);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms < bestt) {
+      bestt = ms;
+      bw = w;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *best = bw;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tuned[key] = bw;
+  return hipSuccess;
+}
+
+static hipError_t autotune(ihdg_ctx* c) {
+  hipError_t e = tune_one(c, false, &c->waves);
+  if (e != hipSuccess) return e;
+  if (c->mixed) return tune_one(c, true, &c->waves32);
+  c->waves32 = c->waves;
+  return hipSuccess;
 }
 
 // n sweeps of the FP64 iterate (ping-pong), followed by the norm reduction of
@@ -629,11 +752,12 @@ static ihdg_status solve_mixed(ihdg_ctx* c, double tol, int32_t* iters, double* 
       HIPCHK(c, read_norms(c, h));
       double inc = std::sqrt(h[0]), nd = std::sqrt(h[1]);
       if (!std::isfinite(inc)) return fail(c, IHDG_ERR_DIVERGED, "non-finite correction");
-      if (inc <= eta * nd || inc == 0.0) break;
+      // enough for the FP64 tolerance, or resolved as far as needed relative to the correction
+      if (inc <= std::max(eta * nd, 0.3 * tol * un) || inc == 0.0) break;
       ibest = std::min(ibest, inc);
       if (inc > 1e3 * ibest) return fail(c, IHDG_ERR_DIVERGED, "correction diverged");
       // FP32 rounding floor: the increment no longer decreases
-      if (inc > 0.9 * prev && inc < 1e-4 * nd) {
+      if (inc > 0.9 * prev && inc < 1e-5 * nd) {
         if (++stall >= 2) break;
       } else {
         stall = 0;
@@ -687,6 +811,20 @@ ihdg_status ihdg_residual(ihdg_ctx* c, double* defect_norm) {
   c->stats.fp64_sweeps -= 1;
   defect_norm[0] = un > 0 ? dn / un : dn;
   defect_norm[1] = dn;
+  return IHDG_OK;
+}
+
+ihdg_status ihdg_time_step(ihdg_ctx* c, int32_t scheme) {
+  if (!c || (scheme != 0 && scheme != 1)) return IHDG_ERR_ARG;
+  if (!c->Ht) return fail(c, IHDG_ERR_UNSUPPORTED, "time stepping needs opts.time_stepping and a shared operator");
+  const double* u = c->u64[c->cur];
+  if (scheme == 0) {
+    HIPCHK(c, launch_time_rhs(c->c64, c->cf, c->Ht, u, c->tmp64, c->sz.n_loc, c->mi.n_blk, 1.0, 0.0, 0.0, c->stream));
+  } else {
+    // tmp = psi(u^n) = c + G x(u^n); then c <- cf + 2 H u - u + (tmp - c)
+    HIPCHK(c, one_sweep(c, false, u, c->tmp64, c->c64));
+    HIPCHK(c, launch_time_rhs(c->c64, c->cf, c->Ht, u, c->tmp64, c->sz.n_loc, c->mi.n_blk, 2.0, -1.0, 1.0, c->stream));
+  }
   return IHDG_OK;
 }
 
@@ -849,7 +987,7 @@ struct BMember {
   int64_t tag;
   int mode;
   int64_t iters;
-  double best, ibest, prev, eta, rel;
+  double best, ibest, prev, eta, rel, unorm;
   int stall;
 };
 
@@ -879,13 +1017,14 @@ static size_t batch_bytes(int32_t mm, int64_t mb, size_t* off_owner, size_t* off
 
 static hipError_t launch_batched(const ihdg_ctx* c, bool fp32, const BatchDesc* d, const int* owner, int64_t nb,
                                  int sidx, hipStream_t s) {
+  const int w = fp32 ? c->waves32 : c->waves;
   switch (c->pde) {
     case IHDG_TRANSPORT:
-      return launch_sweep_batched_transport(c->mi.dim, c->mi.p, fp32, c->shared, c->waves, d, owner, nb, sidx, s);
+      return launch_sweep_batched_transport(c->mi.dim, c->mi.p, fp32, c->shared, w, d, owner, nb, sidx, s);
     case IHDG_SHALLOW_WATER:
-      return launch_sweep_batched_sw(c->mi.p, fp32, c->shared, c->waves, d, owner, nb, sidx, s);
+      return launch_sweep_batched_sw(c->mi.p, fp32, c->shared, w, d, owner, nb, sidx, s);
     case IHDG_CONVDIFF:
-      return launch_sweep_batched_cd(c->mi.p, fp32, c->shared, c->waves, d, owner, nb, sidx, s);
+      return launch_sweep_batched_cd(c->mi.p, fp32, c->shared, w, d, owner, nb, sidx, s);
   }
   return hipErrorInvalidValue;
 }
@@ -955,7 +1094,7 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
     const BMember& m = b->active[i];
     const ihdg_ctx* c = m.c;
     Key k{(int)c->pde, c->mi.dim, c->mi.p, c->shared ? 1 : 0, m.mode == kModeF32 ? 1 : 0,
-          m.mode == kModeDefect ? 1 : 0, c->waves};
+          m.mode == kModeDefect ? 1 : 0, m.mode == kModeF32 ? c->waves32 : c->waves};
     groups[k].push_back(i);
   }
   std::vector<BatchDesc> hd;
@@ -1055,6 +1194,7 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
       else if (m.iters >= c->opt.max_iters) status = IHDG_ERR_MAXITER;
       else {
         m.eta = std::max(c->opt.inner_rtol, std::min(0.1, 0.3 * m.tol * nrm / inc));
+        m.unorm = nrm;
         if (launch_diff_to_f32(c->tmp64, c->u64[c->cur], c->d32, c->nvec, st) != hipSuccess ||
             launch_fill_zero_f32(c->dl32[0], c->nvec, st) != hipSuccess ||
             launch_fill_zero_f32(c->dl32[1], c->nvec, st) != hipSuccess)
@@ -1070,10 +1210,10 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
       if (S % 2) c->cur32 ^= 1;
       bool stop = false;
       if (!std::isfinite(inc)) status = IHDG_ERR_DIVERGED;
-      else if (inc <= m.eta * nrm || inc == 0.0) stop = true;
+      else if (inc <= std::max(m.eta * nrm, 0.3 * m.tol * m.unorm) || inc == 0.0) stop = true;
       else if (inc > 1e3 * (m.ibest = std::min(m.ibest, inc))) status = IHDG_ERR_DIVERGED;
       else {
-        if (inc > 0.9 * m.prev && inc < 1e-4 * nrm) {
+        if (inc > 0.9 * m.prev && inc < 1e-5 * nrm) {
           if (++m.stall >= 2) stop = true;
         } else {
           m.stall = 0;

@@ -29,6 +29,7 @@ struct SetupArgs {
   RefTab rt;
   Coeffs cf;
   int pde, m, n_loc, n_in, m_f;
+  int flux;         // transport: 0 upwind, 1 NPC
   int shared_rep;   // 1: assemble one representative element, all faces treated as interior
   int64_t e0;       // first element of this chunk
   int64_t count;    // elements in this chunk
@@ -93,6 +94,10 @@ __host__ __device__ inline SweepArgs batch_args(const BatchDesc& d, int s) {
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 hipError_t launch_shared_c(const SetupArgs& a, hipStream_t s);
 hipError_t launch_maps(const SetupArgs& a, int* fmap, hipStream_t s);
+hipError_t launch_time_operator(const SetupArgs& a, double* H, hipStream_t s);
+hipError_t launch_time_rhs(double* c, const double* cf, const double* H, const double* u, const double* psi,
+                           int n_loc, int64_t n_blk, double alpha, double beta, double gamma, hipStream_t s);
+hipError_t launch_node_points(const MeshInfo& mi, const RefTab& rt, double* x, hipStream_t s);
 hipError_t launch_quad_points(const MeshInfo& mi, const RefTab& rt, double* xq, double* xfq, hipStream_t s);
 
 // Sweep dispatch: returns hipErrorInvalidValue if (pde, dim, p) has no instance.

@@ -167,13 +167,15 @@ __device__ double entry_L(const SetupArgs& a, const Basis& b, const ElemData& d,
   const int fi = row / np, ni = row % np, fj = col / np, nj = col % np;
   const Coeffs& c = a.cf;
   if (a.pde == kTransport) {
-    // -(u, div(beta v)) + sigma (u, v) + <(beta.n + |beta.n|) u, v>
+    // -(u, div(beta v)) + sigma (u, v) + <(beta.n + tau) u, v>, tau = |beta.n| (upwind)
+    // or max(-beta.n, 0) (NPC), i.e. 2 max(beta.n, 0) or max(beta.n, 0)
+    const double cf = a.flux == 1 ? 1.0 : 2.0;
     double v = convect(b, d, ni, nj) + d.sigma * mass(b, ni, nj);
     for (int f = 0; f < a.mi.nf; ++f) {
       if (!b.on_face(f, ni) || !b.on_face(f, nj)) continue;
       for (int qf = 0; qf < a.mi.nfq; ++qf) {
         double bn = d.bn[f][qf];
-        v += b.Wf(f, qf) * (bn + fabs(bn)) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+        v += b.Wf(f, qf) * cf * fmax(bn, 0.0) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
       }
     }
     return v;
@@ -236,10 +238,12 @@ __device__ double entry_E(const SetupArgs& a, const Basis& b, const ElemData& d,
   const Coeffs& c = a.cf;
   double w[kMaxNfq];
   if (a.pde == kTransport) {
-    // weighted trace |beta.n| uhat on the face; on a boundary face only the outflow part
+    // upwind: weighted trace |beta.n| uhat (own trace on outflow, neighbour's on inflow);
+    // on a boundary face only the outflow part.  NPC: tau uhat, nonzero on inflow only.
     for (int qf = 0; qf < a.mi.nfq; ++qf) {
       double bn = d.bn[f][qf];
-      w[qf] = d.interior[f] ? fabs(bn) : fmax(bn, 0.0);
+      if (a.flux == 1) w[qf] = d.interior[f] ? fmax(-bn, 0.0) : 0.0;
+      else w[qf] = d.interior[f] ? fabs(bn) : fmax(bn, 0.0);
     }
     return face_mass(b, f, ni, nj, w);
   }
@@ -480,6 +484,30 @@ __global__ __launch_bounds__(kST) void k_shared_c(SetupArgs a) {
   }
 }
 
+// Time-stepping operator H = mass_coef * L^{-1} M_Phi (shared operator), M_Phi the
+// block-diagonal mass matrix of the time derivative (times Phi on the
+// shallow-water velocity fields).  One workgroup.
+__global__ __launch_bounds__(kST) void k_time_operator(SetupArgs a, double* H) {
+  __shared__ RefTab rt;
+  if (threadIdx.x == 0) rt = a.rt;
+  __syncthreads();
+  Basis b(rt, a.mi);
+  const int n = a.n_loc, np = a.mi.np;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int r = idx / n, j = idx % n;
+    const int fj = j / np, nj = j % np;
+    const double fac = (a.pde == kShallowWater && fj > 0) ? a.cf.Phi : 1.0;
+    double s = 0.0;
+    for (int k = fj * np; k < (fj + 1) * np; ++k) s += a.Linv[(int64_t)r * n + k] * mass(b, k % np, nj);
+    H[idx] = a.cf.mass_coef * fac * s;
+  }
+}
+
+hipError_t launch_time_operator(const SetupArgs& a, double* H, hipStream_t s) {
+  hipLaunchKernelGGL(k_time_operator, dim3(1), dim3(kST), 0, s, a, H);
+  return hipGetLastError();
+}
+
 // Source map of the gather, fmap[blk][f][lane]:
 //   transport: the element whose trace feeds local face f (itself on an
 //     outflow face, its neighbour on an inflow face, -1 on an inflow boundary
@@ -508,9 +536,9 @@ __global__ void k_maps(SetupArgs a, int* fmap) {
           pos |= bn > 0.0;
           neg |= bn < 0.0;
         }
-        if (!neg) v = (int)e;                  // outflow (or tangential): own trace
-        else if (!pos) v = (int)nb;            // inflow: upwind neighbour, -1 on the boundary
-        else if (nb < 0) v = (int)e;           // mixed boundary face: own trace on outflow points
+        if (!neg) v = a.flux == 1 ? -1 : (int)e;  // outflow (or tangential): own trace (none for NPC)
+        else if (!pos) v = (int)nb;               // inflow: upwind neighbour, -1 on the boundary
+        else if (nb < 0) v = a.flux == 1 ? -1 : (int)e;  // mixed boundary face: own trace on outflow points
         else {
           atomicOr(&a.flags[1], 1);
           v = (int)nb;
@@ -565,6 +593,29 @@ __global__ void k_quad_points(MeshInfo m, RefTab t, double* xq, double* xfq) {
       }
     }
   }
+}
+
+__global__ void k_node_points(MeshInfo m, RefTab t, double* x) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m.n_el * m.np;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    int64_t e = k / m.np;
+    int i = (int)(k % m.np);
+    int ijk[3];
+    el_ijk(m, e, ijk);
+    for (int a = 0; a < m.dim; ++a) {
+      int ia = i % t.n1;
+      i /= t.n1;
+      x[k * m.dim + a] = m.lo[a] + ijk[a] * m.h[a] + 0.5 * m.h[a] * (t.r[ia] + 1.0);
+    }
+  }
+}
+
+hipError_t launch_node_points(const MeshInfo& mi, const RefTab& rt, double* x, hipStream_t s) {
+  int64_t total = mi.n_el * mi.np;
+  unsigned blocks = (unsigned)((total + 255) / 256);
+  if (blocks > 65535u * 16u) blocks = 65535u * 16u;
+  hipLaunchKernelGGL(k_node_points, dim3(blocks), dim3(256), 0, s, mi, rt, x);
+  return hipGetLastError();
 }
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {

@@ -260,13 +260,20 @@ struct Mfma<double> {
   static constexpr int kPad = 8;
 };
 
+// Work split: the (row tile, element tile) pairs i = 0 .. 4 MT - 1, with row tile
+// i % MT and element tile i / MT, go to wave i % NW.  When NW is a multiple of
+// MT every wave keeps a single row tile (one A slice) and NW / MT ... 4 element
+// tiles; otherwise a wave owns whole row tiles w, w + NW, ... and all 4 element
+// tiles.
 template <typename T, int PDE, int DIM, int P, int NW>
 struct MfmaShape {
   static constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
   static constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
   static constexpr int MT = (NLOC + 15) / 16, KT = (NIN + 3) / 4;
-  static constexpr int MTW = (MT + NW - 1) / NW;    // row tiles per wave
-  static constexpr int S = kLanes + Mfma<T>::kPad;  // LDS row stride of X
+  static constexpr bool PAIRS = (NW % MT == 0) && (NW / MT <= 4) && (4 % (NW / MT) == 0);
+  static constexpr int MTW = PAIRS ? 1 : (MT + NW - 1) / NW;  // row tiles per wave
+  static constexpr int NTW = PAIRS ? 4 / (NW / MT) : 4;       // element tiles per wave
+  static constexpr int S = kLanes + Mfma<T>::kPad;            // LDS row stride of X
 };
 
 // this wave's slice of G as MFMA A operands
@@ -279,7 +286,7 @@ __device__ __forceinline__ void mfma_load_a(const SweepArgs& a, T (&av)[MfmaShap
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int t = 0; t < Sh::MTW; ++t) {
-    const int mt = w + t * NW;
+    const int mt = Sh::PAIRS ? w % Sh::MT : w + t * NW;
 #pragma unroll
     for (int ks = 0; ks < Sh::KT; ++ks) {
       const int r = mt * 16 + li, k = ks * 4 + lk;
@@ -314,36 +321,45 @@ __device__ __forceinline__ void mfma_block(const SweepArgs& a, int64_t blk,
   __syncthreads();
   // (c): GEMM on the matrix cores, (d): write + norm partials
   double sd = 0.0, su = 0.0;
+  constexpr int NTW = Sh::NTW;
+  const int nt0 = Sh::PAIRS ? (w / Sh::MT) * NTW : 0;
 #pragma unroll
   for (int t = 0; t < Sh::MTW; ++t) {
-    const int mt = w + t * NW;
+    const int mt = Sh::PAIRS ? w % Sh::MT : w + t * NW;
     if (mt >= Sh::MT) break;
-    v4 acc[4];
+    // c_K and u^k of this tile: loads issued now, consumed after the MFMA chain
+    v4 acc[NTW];
+    T cpre[NTW][4], upre[NTW][4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
+    for (int j = 0; j < NTW; ++j) {
+      const int nt = nt0 + j;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + Mfma<T>::row(lane, r);
-        acc[nt][r] = row < NLOC ? cc[(blk * NLOC + row) * kLanes + nt * 16 + li] : T(0);
+        const int64_t o = (blk * NLOC + row) * kLanes + nt * 16 + li;
+        cpre[j][r] = row < NLOC ? cc[o] : T(0);
+        upre[j][r] = row < NLOC ? uin[o] : T(0);
+        acc[j][r] = T(0);
       }
     }
 #pragma unroll
     for (int ks = 0; ks < Sh::KT; ++ks) {
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt) {
-        const T b = xs[(ks * 4 + lk) * S + nt * 16 + li];
-        acc[nt] = Mfma<T>::mma(av[t][ks], b, acc[nt]);
+      for (int j = 0; j < NTW; ++j) {
+        const T b = xs[(ks * 4 + lk) * S + (nt0 + j) * 16 + li];
+        acc[j] = Mfma<T>::mma(av[t][ks], b, acc[j]);
       }
     }
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
+    for (int j = 0; j < NTW; ++j) {
+      const int nt = nt0 + j;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = mt * 16 + Mfma<T>::row(lane, r);
         if (row < NLOC) {
           const int64_t o = (blk * NLOC + row) * kLanes + nt * 16 + li;
-          const T nv = acc[nt][r];
-          const double dd = (double)nv - (double)uin[o], wt = a.wnorm[row];
+          const T nv = acc[j][r] + cpre[j][r];
+          const double dd = (double)nv - (double)upre[j][r], wt = a.wnorm[row];
           uout[o] = nv;
           sd += wt * dd * dd;
           su += wt * (double)nv * (double)nv;
@@ -399,17 +415,21 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_mfma_batched(const BatchDesc*
 }
 
 template <typename T, int PDE, int DIM, int P>
-hipError_t launch_mfma(const SweepArgs& a, hipStream_t s) {
+hipError_t launch_mfma(int waves, const SweepArgs& a, hipStream_t s) {
   // persistent: a few workgroups per CU loop over the 64-element blocks
   const int64_t g = a.n_blk < 2048 ? a.n_blk : 2048;
-  hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 4>), dim3((unsigned)g), dim3(256), 0, s, a);
+  if (waves == 8) {
+    hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 8>), dim3((unsigned)g), dim3(512), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 4>), dim3((unsigned)g), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <typename T, int PDE, int DIM, int P, bool SHARED>
 hipError_t launch_one(int waves, const SweepArgs& a, hipStream_t s) {
   if constexpr (SHARED) {
-    if (waves != 3) return launch_mfma<T, PDE, DIM, P>(a, s);  // waves == 3: vector-FMA reference variant
+    if (waves != 3) return launch_mfma<T, PDE, DIM, P>(waves, a, s);  // waves == 3: vector-FMA variant
   }
   dim3 grid((unsigned)a.n_blk);
   switch (waves) {

@@ -146,6 +146,27 @@ __global__ __launch_bounds__(256) void k_reduce_batched(const BatchDesc* __restr
   }
 }
 
+// c <- cf + alpha H u + beta u + gamma (psi - c), interleaved layout, shared H
+// (n_loc x n_loc): one thread per (element, row); psi is one sweep of u.
+__global__ __launch_bounds__(256) void k_time_rhs(double* __restrict__ c, const double* __restrict__ cf,
+                                                   const double* __restrict__ H, const double* __restrict__ u,
+                                                   const double* __restrict__ psi, int n_loc, int64_t n_blk,
+                                                   double alpha, double beta, double gamma) {
+  const int64_t total = n_blk * (int64_t)n_loc * kLanes;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = (int)(i % kLanes);
+    const int64_t br = i / kLanes;
+    const int r = (int)(br % n_loc);
+    const int64_t blk = br / n_loc;
+    const double* ue = u + blk * n_loc * kLanes + lane;
+    double hu = 0.0;
+    for (int k = 0; k < n_loc; ++k) hu += H[(int64_t)r * n_loc + k] * ue[(int64_t)k * kLanes];
+    double v = cf[i] + alpha * hu + beta * u[i];
+    if (gamma != 0.0) v += gamma * (psi[i] - c[i]);
+    c[i] = v;
+  }
+}
+
 static unsigned grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 16384) b = 16384;
@@ -187,6 +208,12 @@ hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t 
 }
 hipError_t launch_multi_axpy(double* w, const double* V, const double* h, int k, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n)), dim3(256), 0, s, w, V, h, k, n);
+  return hipGetLastError();
+}
+hipError_t launch_time_rhs(double* c, const double* cf, const double* H, const double* u, const double* psi,
+                           int n_loc, int64_t n_blk, double alpha, double beta, double gamma, hipStream_t s) {
+  hipLaunchKernelGGL(k_time_rhs, dim3(grid_for(n_blk * n_loc * kLanes)), dim3(256), 0, s, c, cf, H, u, psi, n_loc,
+                     n_blk, alpha, beta, gamma);
   return hipGetLastError();
 }
 hipError_t launch_reduce_batched(const BatchDesc* descs, int n, double* norms, hipStream_t s) {

@@ -70,7 +70,9 @@ class Server:
         self.keep = keep_solutions
 
     def _krylov_job(self, rid, problem, tol):
-        torch.cuda.set_device(torch.device(self.device))
+        dev = torch.device(self.device)
+        if dev.index is not None:
+            torch.cuda.set_device(dev.index)
         side = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(side):
             s = make_solver(problem, device=self.device, krylov_restart=self.krylov_restart, max_iters=200000)

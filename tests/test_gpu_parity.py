@@ -165,3 +165,21 @@ def test_sweep_is_deterministic():
     nb = b.sweep(9, norms=True)
     assert na == nb
     assert torch.equal(a.get_solution(), b.get_solution())
+
+
+@pytest.mark.parametrize("make", [lambda: w.config2(n=14, p=3), lambda: w.config3(n=5, p=2)])
+def test_npc_flux_per_sweep_and_exact_termination(make):
+    """NPC flux: per-sweep parity with the oracle's NPC iteration, and the GPU iterate
+    equals the upwind solution after J sweeps (Theorem 2)."""
+    pr = make()
+    o = TransportOperators(pr, flux="npc")
+    ref = TransportOperators(pr).downwind()
+    J = int(o.flow_levels().max()) + 1
+    s = gpu_solver(pr, flux="npc")
+    u = np.zeros_like(ref)
+    for k in range(3):
+        u = o.sweep(u)
+    s.sweep(3)
+    assert rel(o, gpu_u(s), u) < 1e-12
+    s.sweep(J - 3)
+    assert rel(o, gpu_u(s), ref) < 1e-12

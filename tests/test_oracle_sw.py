@@ -67,3 +67,37 @@ def test_conditional_convergence_remark():
     _, k2, hist2 = bad.ihdg(tol=1e-10, max_iters=300, record=True)
     assert k2 == 300 or not np.isfinite(hist2[-1])
     assert hist2[-1] > hist2[len(hist2) // 2]
+
+
+@pytest.mark.parametrize("n,p", [(4, 1), (4, 2), (6, 3), (4, 4)])
+def test_warm_start_two_iterations_per_step_at_tiny_dt(n, p):
+    """Section 5.2: with dt = 1e-6 and the previous step as initial guess, every
+    Crank-Nicolson step takes 2 iHDG iterations, for all meshes and orders."""
+    pr = w.sw_free_wave((n, n), p, 1e-6)
+    o = SWOperators(pr)
+    U = o.nodal(pr.meta["exact_at"](0.0))
+    for _ in range(3):
+        F = o.cn_step_rhs(U)
+        Ui, k, _ = o.solve_with_forcing(F, direct=False, u0=U, tol=1e-10)
+        Ud = o.solve_with_forcing(F)
+        assert k == 2
+        assert h_norm(o.mesh, o.el, Ui - Ud) / h_norm(o.mesh, o.el, Ud) < 1e-9
+        U = Ud
+
+
+def test_crank_nicolson_is_second_order_in_time():
+    """Crank-Nicolson steps (the time discretisation of the paper's experiments) reproduce
+    the exact standing wave with error O(dt^2) when the spatial error is small."""
+    from oracle.norms import l2_error
+    n, p, T = 6, 5, 0.2
+    errs = []
+    for dt in [0.04, 0.02, 0.01]:
+        pr = w.sw_free_wave((n, n), p, dt)
+        o = SWOperators(pr)
+        U = o.nodal(pr.meta["exact_at"](0.0))
+        for _ in range(int(round(T / dt))):
+            U = o.solve_with_forcing(o.cn_step_rhs(U))
+        errs.append(sum(l2_error(o.mesh, o.el, U, lambda x, c=c: pr.meta["exact_at"](T)(x)[..., c], field=c)
+                        for c in range(3)))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.9), rates

@@ -206,3 +206,50 @@ def test_iteration_count_independent_of_p():
         o = TransportOperators(w.transport_const((12, 12), p, (1.0, 0.5), sigma=1.0))
         _, ks[p], _ = o.ihdg(tol=1e-12)
     assert abs(ks[2] - ks[4]) <= 0.1 * ks[2]
+
+
+# ---------------------------------------------------------------------------
+# NPC flux (the flux analysed after Theorem 1; Theorem 2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("make", [lambda: w.config2(n=7, p=3), lambda: w.config3(n=3, p=2),
+                                  lambda: w.transport_affine_beta((5, 6), 2)])
+def test_npc_fixed_point_is_the_upwind_solution(make):
+    pr = make()
+    up, npc = TransportOperators(pr), TransportOperators(pr, flux="npc")
+    ref = up.downwind()
+    u, k, _ = npc.ihdg(tol=1e-14)
+    assert rel(up, u, ref) < 1e-12
+
+
+@pytest.mark.parametrize("make", [lambda: w.config2(n=6, p=2), lambda: w.transport_e2(3, 2),
+                                  lambda: w.transport_e1(5, 3)])
+def test_npc_terminates_after_J_sweeps_theorem2(make):
+    pr = make()
+    npc = TransportOperators(pr, flux="npc")
+    ref = TransportOperators(pr).downwind()
+    J = int(npc.flow_levels().max()) + 1
+    u = np.zeros_like(ref)
+    for _ in range(J - 1):
+        u = npc.sweep(u)
+    assert rel(npc, u, ref) > 1e-6          # not yet
+    u = npc.sweep(u)
+    assert rel(npc, u, ref) < 1e-12         # exact after J sweeps
+
+
+NPC_2D = [(16, 3, 9), (64, 3, 17), (256, 3, 33), (16, 4, 9), (64, 4, 17), (256, 4, 33)]
+
+
+@pytest.mark.parametrize("n_el,p,iters", NPC_2D)
+def test_paper_table1_npc_2d_iteration_counts(n_el, p, iters):
+    """Table 1, NPC column of the 2-D test: 2N+1 iterations on N x N elements (within one)."""
+    n = int(round(np.sqrt(n_el)))
+    o = TransportOperators(w.transport_e1(n, p), flux="npc")
+    M = np.einsum("q,qi,qj->ij", o.el.Wq * o.mesh.jac(), o.el.B, o.el.B)
+    u = np.zeros((o.mesh.n_el, o.el.np))
+    for k in range(1, 500):
+        un = o.sweep(u)
+        d = un - u
+        u = un
+        if np.sqrt(np.einsum("ei,ij,ej->", d, M, d)) < 1e-10:
+            break
+    assert abs(k - iters) <= 1, (k, iters)

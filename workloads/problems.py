@@ -404,3 +404,25 @@ def arrival_times(n, rate, seed=12345):
     """Poisson arrivals: cumulative sums of exponential gaps with mean 1/rate."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def sw_free_wave(n, p, dt, Phi=1.0):
+    """The paper's shallow-water standing wave (Section 5.2): Phi = 1, f = 0,
+    gamma = 0, no forcing, walls; initial state phi = cos(pi x) cos(pi y),
+    u = v = 0; exact solution phi cos(sqrt(2) pi t), u, v as in the paper.
+    One Crank-Nicolson step operator (a = 2) of size dt."""
+    r2 = math.sqrt(2.0)
+
+    def exact_at(t):
+        def ex(x, xp=np):
+            ph = xp.cos(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * math.cos(r2 * PI * t)
+            uu = xp.sin(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * math.sin(r2 * PI * t) / r2
+            vv = xp.cos(PI * x[..., 0]) * xp.sin(PI * x[..., 1]) * math.sin(r2 * PI * t) / r2
+            return xp.stack([ph, uu, vv], -1)
+        return ex
+
+    pr = Problem(pde="sw", dim=2, n=tuple(n), p=p, Phi=Phi, f0=0.0, gamma=0.0, dt=dt, a_mass=2.0,
+                 forcing=lambda x, sigma=None, xp=np: xp.stack([x[..., 0] * 0] * 3, -1),
+                 exact=exact_at(0.0), name=f"sw_wave_{n[0]}x{n[1]}_p{p}")
+    pr.meta["exact_at"] = exact_at
+    return pr
