@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2", "cfg3", "cfg4a", "cfg4b", "serve"])
+    ap.add_argument("--flux", default="upwind", choices=["upwind", "npc"], help="transport trace flux")
     ap.add_argument("--requests", type=int, default=2000, help="serve: number of requests")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrival rate (0 = 0.8 x calibrated)")
     ap.add_argument("--waves", type=int, default=0)
@@ -137,7 +138,7 @@ def serve(args):
     from paper_1605_03228_amd.serving import Server
     n = args.requests
     probs = [w.serving_request(i) for i in range(n)]
-    srv = Server(hbm_budget_bytes=96 << 30, sweeps=16)
+    srv = Server(hbm_budget_bytes=96 << 30, sweeps=16, progress=50)
     rate = args.rate
     calib = None
     if rate <= 0:
@@ -188,7 +189,8 @@ def main():
     dev = "cuda"
     pr = make_problem(args.workload)
     t0 = time.perf_counter()
-    s64 = make_solver(pr, device=dev, block_waves=args.waves)
+    fx = {"flux": args.flux} if pr.pde == "transport" else {}
+    s64 = make_solver(pr, device=dev, block_waves=args.waves, **fx)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     sz = s64.sz
@@ -221,7 +223,7 @@ def main():
 
     # ---- time to tolerance (same tolerance for both paths) ------------------------
     tol = 1e-12 if args.workload == "cfg1" else 1e-10
-    s64b = make_solver(pr, device=dev, block_waves=args.waves)
+    s64b = make_solver(pr, device=dev, block_waves=args.waves, **fx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r64 = s64b.solve(tol)
@@ -230,7 +232,7 @@ def main():
     u64 = s64b.get_solution()
 
     t0 = time.perf_counter()
-    smx = make_solver(pr, device=dev, prec=1, block_waves=args.waves)
+    smx = make_solver(pr, device=dev, prec=1, block_waves=args.waves, **fx)
     torch.cuda.synchronize()
     setup_mx = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -275,7 +277,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded analytic coefficients, manufactured solution)",
-        "config": {"workload": DESCR[args.workload] + " (FP64 sweep timed)",
+        "config": {"workload": DESCR[args.workload] + " (FP64 sweep timed)"
+                   + (", NPC flux" if args.flux == "npc" and pr.pde == "transport" else ""),
                    "n_el": n_el, "n_loc": n_loc, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -35,12 +35,12 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Face values of local face f of element (blk, l) given its face-map entry s.
 template <typename T, int PDE, int DIM, int P, bool SHARED>
-__device__ inline void face_values(const SweepArgs& a, int64_t blk, int f, int l, T* x) {
+__device__ inline void face_values_from(const SweepArgs& a, int64_t blk, int f, int l, int s, T* x) {
   constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
   constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP;
   const T* __restrict__ u = (const T*)a.uin;
-  const int s = a.fmap[(blk * NF + f) * kLanes + l];
   if constexpr (PDE == kTransport) {
     if (s < 0) {
 #pragma unroll
@@ -102,17 +102,23 @@ __device__ inline void face_values(const SweepArgs& a, int64_t blk, int f, int l
       }
 #pragma unroll
       for (int c = 0; c < NFP; ++c) {
+        // one row of the projection: 3 nfp independent loads in flight, then the FMAs
+        T pr[3 * NFP];
+#pragma unroll
+        for (int q = 0; q < 3 * NFP; ++q) pr[q] = Pm[base + (((q / NFP) * NFP + c) * NFP + q % NFP) * str];
         T acc = T(0);
 #pragma unroll
-        for (int b = 0; b < NFP; ++b) {
-          acc += Pm[base + ((0 * NFP + c) * NFP + b) * str] * ds[b];
-          acc += Pm[base + ((1 * NFP + c) * NFP + b) * str] * um[b];
-          acc += Pm[base + ((2 * NFP + c) * NFP + b) * str] * up[b];
-        }
+        for (int b = 0; b < NFP; ++b) acc += pr[b] * ds[b] + pr[NFP + b] * um[b] + pr[2 * NFP + b] * up[b];
         x[c] = acc;
       }
     }
   }
+}
+
+template <typename T, int PDE, int DIM, int P, bool SHARED>
+__device__ inline void face_values(const SweepArgs& a, int64_t blk, int f, int l, T* x) {
+  constexpr int NF = 2 * DIM;
+  face_values_from<T, PDE, DIM, P, SHARED>(a, blk, f, l, a.fmap[(blk * NF + f) * kLanes + l], x);
 }
 
 template <typename T, int PDE, int DIM, int P, bool SHARED>
@@ -274,6 +280,7 @@ struct MfmaShape {
   static constexpr int MTW = PAIRS ? 1 : (MT + NW - 1) / NW;  // row tiles per wave
   static constexpr int NTW = PAIRS ? 4 / (NW / MT) : 4;       // element tiles per wave
   static constexpr int S = kLanes + Mfma<T>::kPad;            // LDS row stride of X
+  static constexpr int PPT = (NF * kLanes + 64 * NW - 1) / (64 * NW);  // (face, element) pairs per thread
 };
 
 // this wave's slice of G as MFMA A operands
@@ -298,9 +305,19 @@ __device__ __forceinline__ void mfma_load_a(const SweepArgs& a, T (&av)[MfmaShap
 // one 64-element block: face step into LDS, GEMM on the matrix cores, write +
 // norm partials.  The padding rows of xs (k >= n_in) must be zero.
 template <typename T, int PDE, int DIM, int P, int NW>
+__device__ __forceinline__ void load_smap(const SweepArgs& a, int64_t blk, int (&smap)[MfmaShape<T, PDE, DIM, P, NW>::PPT]) {
+  typedef MfmaShape<T, PDE, DIM, P, NW> Sh;
+#pragma unroll
+  for (int pp = 0; pp < Sh::PPT; ++pp) {
+    const int fl = threadIdx.x + pp * 64 * NW;
+    smap[pp] = (fl < Sh::NF * kLanes && blk < a.n_blk) ? a.fmap[(blk * Sh::NF + (fl >> 6)) * kLanes + (fl & 63)] : -1;
+  }
+}
+
+template <typename T, int PDE, int DIM, int P, int NW>
 __device__ __forceinline__ void mfma_block(const SweepArgs& a, int64_t blk,
                                            const T (&av)[MfmaShape<T, PDE, DIM, P, NW>::MTW][MfmaShape<T, PDE, DIM, P, NW>::KT],
-                                           T* xs, double* red) {
+                                           const int (&smap)[MfmaShape<T, PDE, DIM, P, NW>::PPT], T* xs, double* red) {
   typedef MfmaShape<T, PDE, DIM, P, NW> Sh;
   typedef typename Mfma<T>::v4 v4;
   constexpr int NFP = Sh::NFP, NLOC = Sh::NLOC, S = Sh::S;
@@ -310,13 +327,26 @@ __device__ __forceinline__ void mfma_block(const SweepArgs& a, int64_t blk,
   T* __restrict__ uout = (T*)a.uout;
   const T* __restrict__ cc = (const T*)a.c;
   const int li = lane & 15, lk = lane >> 4;
-  // (a) + (b): face step writes x[k][element] into LDS (row stride S)
-  for (int fl = tid; fl < Sh::NF * kLanes; fl += 64 * NW) {
-    T tmp[NFP];
-    const int f = fl >> 6, l = fl & 63;
-    face_step_to<T, PDE, DIM, P>(a, blk, f, l, tmp);
+  // (a) + (b): face step writes x[k][element] into LDS (row stride S).  The
+  // thread's face-map entries (smap, prefetched by the caller) are all known,
+  // so every trace load of its (face, element) pairs is issued before any LDS
+  // write.
+  constexpr int PPT = Sh::PPT;
+  {
+    T tmp[PPT][NFP];
 #pragma unroll
-    for (int t = 0; t < NFP; ++t) xs[(f * NFP + t) * S + l] = tmp[t];
+    for (int pp = 0; pp < PPT; ++pp) {
+      const int fl = tid + pp * 64 * NW;
+      if (fl < Sh::NF * kLanes) face_values_from<T, PDE, DIM, P, true>(a, blk, fl >> 6, fl & 63, smap[pp], tmp[pp]);
+    }
+#pragma unroll
+    for (int pp = 0; pp < PPT; ++pp) {
+      const int fl = tid + pp * 64 * NW;
+      if (fl < Sh::NF * kLanes) {
+#pragma unroll
+        for (int t = 0; t < NFP; ++t) xs[((fl >> 6) * NFP + t) * S + (fl & 63)] = tmp[pp][t];
+      }
+    }
   }
   __syncthreads();
   // (c): GEMM on the matrix cores, (d): write + norm partials
@@ -393,8 +423,14 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_mfma(SweepArgs a) {
   T av[Sh::MTW][Sh::KT];
   mfma_load_a<T, PDE, DIM, P, NW>(a, av);
   for (int i = threadIdx.x; i < (Sh::KT * 4 - Sh::NIN) * Sh::S; i += 64 * NW) xs[Sh::NIN * Sh::S + i] = T(0);
+  int smap[Sh::PPT];
+  load_smap<T, PDE, DIM, P, NW>(a, blockIdx.x, smap);
   for (int64_t blk = blockIdx.x; blk < a.n_blk; blk += gridDim.x) {
-    mfma_block<T, PDE, DIM, P, NW>(a, blk, av, xs, red);
+    int cur[Sh::PPT];
+#pragma unroll
+    for (int pp = 0; pp < Sh::PPT; ++pp) cur[pp] = smap[pp];
+    load_smap<T, PDE, DIM, P, NW>(a, blk + gridDim.x, smap);  // next block's face map, in flight meanwhile
+    mfma_block<T, PDE, DIM, P, NW>(a, blk, av, cur, xs, red);
     __syncthreads();  // xs and red are reused by the next block
   }
 }
@@ -411,7 +447,10 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_mfma_batched(const BatchDesc*
   T av[Sh::MTW][Sh::KT];
   mfma_load_a<T, PDE, DIM, P, NW>(a, av);
   for (int i = threadIdx.x; i < (Sh::KT * 4 - Sh::NIN) * Sh::S; i += 64 * NW) xs[Sh::NIN * Sh::S + i] = T(0);
-  mfma_block<T, PDE, DIM, P, NW>(a, (int64_t)blockIdx.x - d.blk0, av, xs, red);
+  const int64_t blk = (int64_t)blockIdx.x - d.blk0;
+  int smap[Sh::PPT];
+  load_smap<T, PDE, DIM, P, NW>(a, blk, smap);
+  mfma_block<T, PDE, DIM, P, NW>(a, blk, av, smap, xs, red);
 }
 
 template <typename T, int PDE, int DIM, int P>

@@ -6,8 +6,9 @@ being solved.  The loop
 * moves arrived requests into a FIFO queue;
 * admits the head of the queue while its device footprint (the library's
   workspace plus its setup scratch, from ihdg_footprint) fits in the HBM
-  budget left and the batch has a free slot; admission runs the request's
-  setup (ihdg_setup) and adds its context to the running batch;
+  budget left and the batch has a free slot; the request's setup
+  (coefficients + ihdg_setup) runs on a setup thread with a stream of its
+  own, and the ready context joins the running batch between rounds;
 * runs one batch round (ihdg_batch_round): every active request advances by
   `sweeps` sweeps, requests of the same shape sharing one kernel launch per
   sweep, all of them resident on the device at once;
@@ -59,7 +60,8 @@ def needs_krylov(problem):
 
 class Server:
     def __init__(self, hbm_budget_bytes=64 << 30, sweeps=16, max_members=256, max_blocks=1 << 22,
-                 device="cuda", krylov_workers=2, krylov_restart=40, keep_solutions=False):
+                 device="cuda", krylov_workers=3, krylov_restart=40, keep_solutions=False, progress=0,
+                 setup_workers=2):
         self.budget = hbm_budget_bytes
         self.sweeps = sweeps
         self.max_members = max_members
@@ -68,6 +70,8 @@ class Server:
         self.krylov_workers = krylov_workers
         self.krylov_restart = krylov_restart
         self.keep = keep_solutions
+        self.progress = progress
+        self.setup_workers = setup_workers
 
     def _krylov_job(self, rid, problem, tol):
         dev = torch.device(self.device)
@@ -81,6 +85,16 @@ class Server:
             s.close()
         return res, u
 
+    def _setup_job(self, problem):
+        dev = torch.device(self.device)
+        if dev.index is not None:
+            torch.cuda.set_device(dev.index)
+        side = torch.cuda.Stream(device=self.device)
+        with torch.cuda.stream(side):
+            s = make_solver(problem, device=self.device, prec=MIXED, check_every=self.sweeps)
+            side.synchronize()
+        return s
+
     def serve(self, requests):
         """requests: iterable of (rid, arrival_s, problem, tol).  Returns a dict with
         per-request records and latency/throughput summaries."""
@@ -88,7 +102,9 @@ class Server:
         waiting = collections.deque()
         batch = Batch(self.max_members, self.max_blocks, self.device)
         pool = ThreadPoolExecutor(self.krylov_workers)
+        setup_pool = ThreadPoolExecutor(self.setup_workers)
         futures = {}
+        setups = {}
         mem = {}
         probs = {}
         used = 0
@@ -109,9 +125,14 @@ class Server:
             if sol is not None:
                 r["solution"] = sol
             used -= mem.pop(rid)
+            done_count[0] += 1
+            if self.progress and done_count[0] % self.progress == 0:
+                print(f"[serve] {done_count[0]} done at t={r['finish']:.1f}s, latency {r['latency']:.3f}s, "
+                      f"active {len(batch.members)} + {len(futures)} krylov, queue {len(waiting)}", flush=True)
 
+        done_count = [0]
         rounds = 0
-        while pending or waiting or batch.members or futures:
+        while pending or waiting or batch.members or futures or setups:
             t = now()
             while pending and pending[0][1] <= t:
                 rid, arr, pr, tol = pending.popleft()
@@ -127,7 +148,7 @@ class Server:
                 need = footprint_bytes(pr, **opts)
                 if used + need > self.budget and used > 0:
                     break
-                if not kry and len(batch.members) >= self.max_members:
+                if not kry and len(batch.members) + len(setups) >= self.max_members:
                     break
                 waiting.popleft()
                 used += need
@@ -137,9 +158,14 @@ class Server:
                 if kry:
                     futures[pool.submit(self._krylov_job, rid, pr, tol)] = rid
                 else:
-                    s = make_solver(pr, device=self.device, prec=MIXED, check_every=self.sweeps)
-                    rec[rid]["n_loc"] = s.sz["n_loc"]
-                    batch.add(s, tol, rid)
+                    setups[setup_pool.submit(self._setup_job, pr)] = (rid, tol)
+            # contexts whose setup has finished join the batch
+            for f in [f for f in setups if f.done()]:
+                rid, tol = setups.pop(f)
+                s = f.result()
+                rec[rid]["n_loc"] = s.sz["n_loc"]
+                rec[rid]["ready"] = now()
+                batch.add(s, tol, rid)
             peak_active = max(peak_active, len(batch.members) + len(futures))
             progressed = False
             if batch.members:
@@ -171,6 +197,7 @@ class Server:
                 nxt = pending[0][1] - now() if pending else 0.002
                 time.sleep(min(max(nxt, 0.0), 0.002))
         pool.shutdown()
+        setup_pool.shutdown()
         batch.close()
         wall = now()
         lat = np.array([r["latency"] for r in rec.values()])
