@@ -59,23 +59,24 @@ def algorithmic_bytes_per_element(n_loc, n_in, nf, fp, shared, proj=0):
     return (0 if shared else n_loc * n_in * fp) + 3 * n_loc * fp + nf * 4 + proj * fp
 
 
-def counter_traffic(key):
+def counter_traffic(key, waves):
     """HBM bytes per launch from the committed counter runs, if the sweep source
-    has not changed since they were taken (else None)."""
+    has not changed since they were taken and the timed launch shape is the one
+    they were taken on (else None)."""
     try:
         with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
             d = json.load(f)[key]
         with open(os.path.join(ROOT, "paper_1605_03228_amd", "csrc", "sweep_impl.hpp"), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
-        return d["traffic_bytes"] if sha == d["source_sha16"] else None
+        return d["traffic_bytes"] if (sha == d["source_sha16"] and waves == d["waves"]) else None
     except (OSError, KeyError, ValueError):
         return None
 
 
-KEYS = {"cfg2": "k_sweep<double, transport, 2, 4, per-element>"}
 KERNEL = {"cfg1": "k_sweep_mfma<double, transport, 2, 2>", "cfg2": "k_sweep<double, transport, 2, 4, per-element>",
           "cfg3": "k_sweep_mfma<double, transport, 3, 3>", "cfg4a": "k_sweep_mfma<double, shallow water, 2, 3>",
           "cfg4b": "k_sweep<double, conv.-diff., 2, 4, per-element>"}
+KEYS = {w: KERNEL[w] for w in ("cfg2", "cfg3", "cfg4b")}
 
 
 def make_problem(name):
@@ -220,6 +221,7 @@ def main():
     achieved = bpe64 * n_el / (t / args.steps) / 1e9
     flops_el = 2 * n_loc * n_in
     tflops = flops_el * n_el / (t / args.steps) / 1e12
+    kw = s64.stats()["kernel_waves"]
 
     # ---- time to tolerance (same tolerance for both paths) ------------------------
     tol = 1e-12 if args.workload == "cfg1" else 1e-10
@@ -282,7 +284,8 @@ def main():
                    "n_el": n_el, "n_loc": n_loc, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (counter_traffic(KEYS.get(args.workload)) if args.waves in (0, 4) else None),
+                     "traffic": counter_traffic(KEYS.get(args.workload), kw),
+                     "kernel_waves": kw,
                      "bytes_per_element": bpe64, "flops_per_element": flops_el, "achieved_tflops": tflops,
                      "kernel": KERNEL[args.workload]},
         "fp64": {"setup_s": setup_s, "solve_tol": tol, "time_to_tol_s": ttt64, "sweeps": r64["iters"],
