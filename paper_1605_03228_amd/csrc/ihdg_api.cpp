@@ -328,6 +328,16 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   const bool shared = decide_shared(pde, coeffs, &o);
   const bool mixed = o.prec == IHDG_MIXED;
   if (o.time_stepping && !shared) return IHDG_ERR_UNSUPPORTED;
+  switch (o.block_waves) {
+    case 0: case 1: case 2: case 4: case 8: break;
+    case 3:
+      if (!shared) return IHDG_ERR_UNSUPPORTED;
+      break;
+    case 5:
+      if (!shared || pde != IHDG_TRANSPORT || !ihdg::direct_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
+      break;
+    default: return IHDG_ERR_ARG;
+  }
   Layout L = make_layout(mi, sz, shared, mixed, o.krylov_restart, o.time_stepping != 0);
   if (workspace_bytes < L.total) return IHDG_ERR_NOMEM;
   const size_t ncol = shared ? (size_t)(2 * sz.n_loc + sz.n_in) : (size_t)(sz.n_loc + sz.n_in + 1);
@@ -565,6 +575,7 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
     }
   }
   std::vector<int> cand = c->shared ? std::vector<int>{4, 8, 3} : std::vector<int>{1, 2, 4, 8};
+  if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::direct_supported(c->mi.dim, c->mi.p)) cand.push_back(5);
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return e;

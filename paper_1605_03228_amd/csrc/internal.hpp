@@ -108,6 +108,10 @@ hipError_t launch_sweep_transport(int dim, int p, bool fp32, bool shared, int wa
 hipError_t launch_sweep_sw(int p, bool fp32, bool shared, int waves, const SweepArgs& a, hipStream_t s);
 hipError_t launch_sweep_cd(int p, bool fp32, bool shared, int waves, const SweepArgs& a, hipStream_t s);
 
+// True where the transport matrix-core variant without LDS staging (launch
+// shape 5, shared operators only) has an instance.
+bool direct_supported(int dim, int p);
+
 hipError_t launch_sweep_batched_transport(int dim, int p, bool fp32, bool shared, int waves, const BatchDesc* d,
                                           const int* owner, int64_t nb, int sidx, hipStream_t s);
 hipError_t launch_sweep_batched_sw(int p, bool fp32, bool shared, int waves, const BatchDesc* d, const int* owner,

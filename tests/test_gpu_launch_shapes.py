@@ -1,0 +1,131 @@
+"""Every launch shape of the sweep kernels against the oracle.
+
+The autotuner picks one launch shape per problem shape; these tests force each
+of them (block_waves) so that every kernel variant is checked on meshes of
+several 64-element blocks with a ragged last block:
+
+* per-element operators: 1, 2, 4, 8 waves per block;
+* shared operators: 4 and 8 waves (matrix cores, traces staged in LDS),
+  3 (vector FMA), 5 (transport only: matrix cores fed straight from the
+  iterate, no LDS staging).
+
+Bar: one sweep is an affine map applied in FP64, so after a few sweeps the
+iterates agree with the oracle's to rounding (1e-12 relative in the h-norm);
+mixed-precision solves agree with the oracle's solution to 1e-8.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle.norms import h_norm
+from oracle.transport import TransportOperators
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_03228_amd import binding
+    binding.load()
+
+
+def _solver(pr, **kw):
+    from paper_1605_03228_amd.problem_io import make_solver
+    print(f"[gpu] {pr.name} n={pr.n} p={pr.p} {kw}", flush=True)
+    return make_solver(pr, **kw)
+
+
+def _u(s):
+    u = s.get_solution()
+    torch.cuda.synchronize()
+    return u.reshape(u.shape[0], -1).cpu().numpy()
+
+
+def _rel(o, a, b):
+    return h_norm(o.mesh, o.el, a - b) / h_norm(o.mesh, o.el, b)
+
+
+def _ragged_cfg2():
+    base = w.config2(n=13, p=3)
+    return w.Problem(**{**base.__dict__, "n": (13, 11), "sigma_el": base.sigma_el[:143]})
+
+
+SHARED = [
+    ("2d_19x13_p2", lambda: w.transport_const((19, 13), 2, (1.0, 0.5))),
+    ("2d_11x9_p6", lambda: w.transport_const((11, 9), 6, (-0.6, 0.8))),
+    ("3d_9cube_p1", lambda: w.config3(n=9, p=1)),
+    ("3d_7cube_p2", lambda: w.config3(n=7, p=2)),
+    ("3d_5cube_p3", lambda: w.config3(n=5, p=3)),
+]
+SHAPES = [(name, make, wv, {}) for name, make in SHARED for wv in (3, 4, 5, 8)]
+SHAPES += [("cfg2_13x11_p3_per_el", _ragged_cfg2, wv, {}) for wv in (1, 2, 4, 8)]
+SHAPES += [("3d_4cube_p4_shared", lambda: w.config3(n=4, p=4), wv, {}) for wv in (3, 4, 8)]
+
+
+@pytest.mark.parametrize("name,make,waves,kw", SHAPES, ids=[f"{c[0]}-w{c[2]}" for c in SHAPES])
+def test_launch_shape_per_sweep(name, make, waves, kw):
+    pr = make()
+    o = TransportOperators(pr)
+    s = _solver(pr, block_waves=waves, **kw)
+    assert s.stats()["kernel_waves"] == waves
+    u = np.zeros((o.mesh.n_el, s.sz["n_loc"]))
+    for k in (1, 2):
+        s.sweep(k)
+        for _ in range(k):
+            u = o.sweep(u)
+        r = _rel(o, _u(s), u)
+        assert r < 1e-12, (k, r)
+    s.close()
+
+
+@pytest.mark.parametrize("name,make", [SHARED[1], SHARED[4]], ids=[SHARED[1][0], SHARED[4][0]])
+def test_direct_variant_mixed_precision_solve(name, make):
+    pr = make()
+    o = TransportOperators(pr)
+    s = _solver(pr, block_waves=5, prec=1)
+    res = s.solve(1e-10)
+    assert res["status"] == 0, res
+    assert _rel(o, _u(s), o.downwind()) < 1e-8
+    s.close()
+
+
+def test_direct_variant_batched_equals_single_bitwise():
+    from paper_1605_03228_amd import Batch
+    items = [w.config3(n=5, p=3), w.transport_const((19, 13), 2, (1.0, 0.5)), w.config3(seed=2, n=6, p=3)]
+    singles = []
+    for pr in items:
+        s = _solver(pr, block_waves=5)
+        res = s.solve(1e-11)
+        singles.append((res["iters"], _u(s)))
+        s.close()
+    b = Batch(max_members=8)
+    for i, pr in enumerate(items):
+        b.add(_solver(pr, block_waves=5), 1e-11, i)
+    got = {}
+    for _ in range(100000):
+        n = b.round(16)
+        for r in b.poll():
+            got[r["tag"]] = (r["iters"], _u(r["solver"]))
+            r["solver"].close()
+        if n == 0:
+            break
+    b.close()
+    for i in range(len(items)):
+        assert got[i][0] == singles[i][0]
+        assert np.array_equal(got[i][1], singles[i][1]), i
+
+
+def test_launch_shape_validation():
+    from paper_1605_03228_amd.binding import IhdgError
+    cases = [(w.sw_standing_wave((6, 6), 2, f0=0.3), 5, 2),       # direct variant: transport only
+             (w.config3(n=3, p=4), 5, 2),                         # operator too large for its LDS layout
+             (_ragged_cfg2(), 3, 2),                              # vector-FMA shared variant, per-element operators
+             (_ragged_cfg2(), 5, 2),
+             (w.config1(), 6, 1), (w.config1(), -1, 1)]           # not a launch shape
+    for pr, wv, status in cases:
+        with pytest.raises(IhdgError) as e:
+            _solver(pr, block_waves=wv)
+        assert e.value.status == status, (pr.name, wv)
