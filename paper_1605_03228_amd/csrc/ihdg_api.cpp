@@ -43,8 +43,7 @@ struct ihdg_ctx {
   double* Ht;        // time stepping: H = mass_coef L^{-1} M_Phi (shared), or null
   double* cf;        // time stepping: the forcing part of c, A^{-1} F
   double* kry;       // Krylov basis, (m+1) vectors (or null)
-  double* kry_part;  // partials for the Krylov dot products
-  double** kry_ptrs; // device array of pointers for the dots kernel
+  double* kry_part;  // Krylov scratch: dot partials, Hessenberg columns, coefficients
   int cur;
   int cur32;
   int waves;    // launch shape of the FP64 sweep kernel (waves per block; 3 = vector-FMA shared variant)
@@ -170,7 +169,7 @@ constexpr int kMaxRestart = 256;
 struct Layout {
   size_t off_Ht, off_cf;
   size_t off_u[2], off_c, off_tmp, off_G64, off_G32, off_Linv, off_P64, off_P32, off_d32, off_dl[2], off_fmap,
-      off_w, off_part, off_norms, off_flags, off_kry, off_krypart, off_kryptr;
+      off_w, off_part, off_norms, off_flags, off_kry, off_krypart;
   size_t total;
   size_t scratch;
   int64_t chunk;
@@ -215,8 +214,10 @@ static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared
   }
   if (krylov > 0) {
     L.off_kry = take(nvec * 8 * (size_t)(krylov + 1));
-    L.off_krypart = take((size_t)m.n_blk * 16 * 8 + (size_t)(krylov + 1) * 8);
-    L.off_kryptr = take(16 * sizeof(double*));
+    // dot partials (kDotGroups x (m+1)), Hessenberg columns ((m+1) x m), the
+    // current Gram-Schmidt coefficients (m+1), 8 scalars, solution coefficients (m)
+    const size_t m1 = (size_t)krylov + 1;
+    L.off_krypart = take(((size_t)ihdg::kDotGroups * m1 + m1 * (size_t)krylov + m1 + 8 + (size_t)krylov) * 8);
   }
   L.total = o;
   // setup scratch: augmented matrices of a chunk of elements
@@ -378,7 +379,6 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   c->cf = (o.time_stepping && shared) ? (double*)(ws + L.off_cf) : nullptr;
   c->kry = o.krylov_restart > 0 ? (double*)(ws + L.off_kry) : nullptr;
   c->kry_part = o.krylov_restart > 0 ? (double*)(ws + L.off_krypart) : nullptr;
-  c->kry_ptrs = o.krylov_restart > 0 ? (double**)(ws + L.off_kryptr) : nullptr;
   c->cur = 0;
   c->cur32 = 0;
   c->sqrt_phi = pde == IHDG_SHALLOW_WATER ? std::sqrt(coeffs->Phi) : 0.0;
@@ -858,69 +858,75 @@ ihdg_status ihdg_set_solution(ihdg_ctx* c, const double* u_dev) {
 // The operator is applied as  v -> v - (psi(v) - c) = v - psi(v) + psi(0);
 // psi(0) = c_K, so  (I - T) v = v - psi(v) + c.  Inner products use the
 // h-norm weights.  The initial guess is the current iterate.
+//
+// The Arnoldi steps run on the device: classical Gram-Schmidt done twice,
+// each pass one batch of dot products into the Hessenberg column and one fused
+// update w -= V h, then the norm and the normalisation, all stream-ordered
+// with no host round trip.  The host reads the new Hessenberg columns every
+// kCheck steps, applies the Givens rotations and tests the residual estimate;
+// steps enqueued past convergence are discarded (their basis vectors are not
+// used in the update).
 // ---------------------------------------------------------------------------
 static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
+  constexpr int kCheck = 8;
   const int m = c->opt.krylov_restart;
+  const int m1 = m + 1;
   const int64_t N = c->nvec;
+  const int n_loc = c->sz.n_loc;
+  hipStream_t st = c->stream;
   double* V = c->kry;  // (m+1) vectors
   auto vec = [&](int j) { return V + (size_t)j * N; };
-  std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hcol(m + 1);
-  std::vector<double*> hptr(16);
+  double* part = c->kry_part;                              // kDotGroups x (m+1)
+  double* Hc = part + (size_t)ihdg::kDotGroups * m1;       // column j at Hc + j (m+1)
+  double* hcur = Hc + (size_t)m1 * m;                      // this pass's coefficients
+  double* scal = hcur + m1;                                // [0]: squared norm
+  double* ydev = scal + 8;                                 // update coefficients
+  std::vector<double> H((size_t)m1 * m), cs(m), sn(m), g(m1), y(m), ny(m);
   int64_t it = 0;
   double rel = INFINITY;
   double* u = c->u64[c->cur];
   double* tmp = c->tmp64;
-  double* hdev = c->kry_part + (size_t)c->mi.n_blk * 16;  // device copy of a Hessenberg column
-  // <x, y_j>_h for the vectors y_0..y_{k-1} (device pointer list), k <= 16
-  auto dots_with = [&](const double* x, const double* const* ys, int k, double* out) -> hipError_t {
-    for (int j = 0; j < k; ++j) hptr[j] = const_cast<double*>(ys[j]);
-    hipError_t e = hipMemcpyAsync(c->kry_ptrs, hptr.data(), k * sizeof(double*), hipMemcpyHostToDevice, c->stream);
+  auto norm2 = [&](const double* x, double* out) -> hipError_t {
+    hipError_t e = launch_kdots(x, x, N, 1, c->wnorm, n_loc, part, scal, nullptr, 0, st);
     if (e != hipSuccess) return e;
-    e = launch_dots(x, (const double* const*)c->kry_ptrs, k, c->wnorm, c->sz.n_loc, c->mi.n_blk, c->kry_part,
-                    c->norms, c->stream);
+    e = hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(out, c->norms, k * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(c->stream);
-  };
-  // <x, V_j>_h for j < k, in chunks of 16
-  auto dots = [&](const double* x, int k, double* out) -> hipError_t {
-    for (int j0 = 0; j0 < k; j0 += 16) {
-      const double* ys[16];
-      int kk = std::min(16, k - j0);
-      for (int j = 0; j < kk; ++j) ys[j] = vec(j0 + j);
-      hipError_t e = dots_with(x, ys, kk, out + j0);
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-  };
-  auto selfdot = [&](const double* x, double* out) -> hipError_t {
-    const double* ys[1] = {x};
-    return dots_with(x, ys, 1, out);
+    return hipStreamSynchronize(st);
   };
   // A v = v - psi(v) + c  written into out
   auto apply = [&](const double* v, double* out) -> hipError_t {
     hipError_t e = one_sweep(c, false, v, out, c->c64);
     if (e != hipSuccess) return e;
     c->stats.fp64_sweeps += 1;
-    e = launch_axpby(out, -1.0, v, 1.0, N, c->stream);  // out = v - psi(v)
-    if (e != hipSuccess) return e;
-    return launch_axpby(out, 1.0, c->c64, 1.0, N, c->stream);  // + c
+    return launch_kapply(out, v, c->c64, N, st);
+  };
+  // one Arnoldi step: V_{j+1} from V_j, Hessenberg column j on the device
+  auto arnoldi = [&](int j) -> hipError_t {
+    double* w = vec(j + 1);
+    double* hcol = Hc + (size_t)j * m1;
+    hipError_t e = apply(vec(j), w);
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+      e = launch_kdots(w, V, N, j + 1, c->wnorm, n_loc, part, hcur, hcol, pass, st);
+      if (e == hipSuccess) e = launch_multi_axpy(w, V, hcur, j + 1, N, st);
+    }
+    if (e == hipSuccess) e = launch_kdots(w, w, N, 1, c->wnorm, n_loc, part, scal, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_knormalize(w, N, scal, hcol + j + 1, st);
+    return e;
   };
   double bnorm;
   {
     double d;
-    HIPCHK(c, selfdot(c->c64, &d));
+    HIPCHK(c, norm2(c->c64, &d));
     bnorm = std::sqrt(std::max(d, 0.0));
   }
   if (bnorm == 0.0) bnorm = 1.0;
   while (it < c->opt.max_iters) {
     // r = c - A u  -> V0
     HIPCHK(c, apply(u, tmp));
-    HIPCHK(c, hipMemcpyAsync(vec(0), c->c64, N * 8, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, launch_axpby(vec(0), 1.0, tmp, -1.0, N, c->stream));
+    HIPCHK(c, hipMemcpyAsync(vec(0), c->c64, N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, launch_axpby(vec(0), 1.0, tmp, -1.0, N, st));
     double rr;
-    HIPCHK(c, selfdot(vec(0), &rr));
+    HIPCHK(c, norm2(vec(0), &rr));
     double beta = std::sqrt(std::max(rr, 0.0));
     rel = beta / bnorm;
     if (final_incr) *final_incr = rel;
@@ -929,54 +935,56 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
       if (iters) *iters = (int32_t)it;
       return IHDG_OK;
     }
-    HIPCHK(c, launch_axpby(vec(0), 1.0 / beta, vec(0), 0.0, N, c->stream));
+    HIPCHK(c, launch_axpby(vec(0), 1.0 / beta, vec(0), 0.0, N, st));
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    int j = 0;
-    for (; j < m && it < c->opt.max_iters; ++j, ++it) {
-      HIPCHK(c, apply(vec(j), vec(j + 1)));
-      // classical Gram-Schmidt, done twice for stability; each pass is one
-      // batch of dot products and one fused update w -= V h
-      for (int pass = 0; pass < 2; ++pass) {
-        HIPCHK(c, dots(vec(j + 1), j + 1, hcol.data()));
-        for (int i = 0; i <= j; ++i) H[i * m + j] = (pass == 0 ? 0.0 : H[i * m + j]) + hcol[i];
-        HIPCHK(c, hipMemcpyAsync(hdev, hcol.data(), (j + 1) * sizeof(double), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, launch_multi_axpy(vec(j + 1), vec(0), hdev, j + 1, N, c->stream));
-      }
-      double nn;
-      HIPCHK(c, selfdot(vec(j + 1), &nn));
-      double hn = std::sqrt(std::max(nn, 0.0));
-      H[(j + 1) * m + j] = hn;
-      if (hn > 0) HIPCHK(c, launch_axpby(vec(j + 1), 1.0 / hn, vec(j + 1), 0.0, N, c->stream));
-      // Givens rotations
-      for (int i = 0; i < j; ++i) {
-        double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-        H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-        H[i * m + j] = t;
-      }
-      double a = H[j * m + j], b = H[(j + 1) * m + j];
-      double r = std::hypot(a, b);
-      cs[j] = r > 0 ? a / r : 1.0;
-      sn[j] = r > 0 ? b / r : 0.0;
-      H[j * m + j] = r;
-      H[(j + 1) * m + j] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      c->stats.krylov_iters += 1;
-      rel = std::fabs(g[j + 1]) / bnorm;
-      if (rel <= tol) {
-        ++j;
+    int used = 0;  // basis vectors entering the update
+    bool conv = false;
+    for (int j0 = 0; j0 < m && !conv && it < c->opt.max_iters;) {
+      const int j1 = (int)std::min<int64_t>({(int64_t)m, (int64_t)j0 + kCheck, (int64_t)j0 + (c->opt.max_iters - it)});
+      for (int j = j0; j < j1; ++j) HIPCHK(c, arnoldi(j));
+      HIPCHK(c, hipMemcpyAsync(H.data() + (size_t)j0 * m1, Hc + (size_t)j0 * m1, (size_t)(j1 - j0) * m1 * 8,
+                               hipMemcpyDeviceToHost, st));
+      HIPCHK(c, hipStreamSynchronize(st));
+      for (int j = j0; j < j1; ++j) {
+        double* h = H.data() + (size_t)j * m1;  // column j: h[i] = H(i, j)
+        for (int i = 0; i < j; ++i) {
+          const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+          h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+          h[i] = t;
+        }
+        const double a = h[j], b = h[j + 1];
+        const double r = std::hypot(a, b);
+        cs[j] = r > 0 ? a / r : 1.0;
+        sn[j] = r > 0 ? b / r : 0.0;
+        h[j] = r;
+        h[j + 1] = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        c->stats.krylov_iters += 1;
         ++it;
-        break;
+        used = j + 1;
+        rel = std::fabs(g[j + 1]) / bnorm;
+        if (!std::isfinite(rel)) return fail(c, IHDG_ERR_DIVERGED, "non-finite Krylov residual");
+        if (rel <= tol) {
+          conv = true;
+          break;
+        }
       }
+      j0 = j1;
     }
-    // solve H y = g and update u += V y
-    for (int i = j - 1; i >= 0; --i) {
+    // solve the triangular system H y = g and update u += V y
+    for (int i = used - 1; i >= 0; --i) {
       double s = g[i];
-      for (int k = i + 1; k < j; ++k) s -= H[i * m + k] * y[k];
-      y[i] = s / H[i * m + i];
+      for (int k = i + 1; k < used; ++k) s -= H[(size_t)k * m1 + i] * y[k];
+      y[i] = s / H[(size_t)i * m1 + i];
     }
-    for (int i = 0; i < j; ++i) HIPCHK(c, launch_axpby(u, 1.0, vec(i), y[i], N, c->stream));
+    if (used > 0) {
+      for (int i = 0; i < used; ++i) ny[i] = -y[i];  // the fused update subtracts
+      HIPCHK(c, hipMemcpyAsync(ydev, ny.data(), used * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(c, launch_multi_axpy(u, V, ydev, used, N, st));
+      HIPCHK(c, hipStreamSynchronize(st));  // y is host memory the next copy may reuse
+    }
     if (iters) *iters = (int32_t)it;
   }
   return fail(c, IHDG_ERR_MAXITER, "max_iters reached");

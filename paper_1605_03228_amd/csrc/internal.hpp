@@ -131,7 +131,14 @@ hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t 
 hipError_t launch_multi_axpy(double* w, const double* V, const double* h, int k, int64_t n, hipStream_t s);
 // norms[2 i + j] = sum over member i's blocks of its partials (fixed order)
 hipError_t launch_reduce_batched(const BatchDesc* descs, int n, double* norms, hipStream_t s);
-hipError_t launch_dots(const double* x, const double* const* ys, int k, const double* w, int n_loc,
-                       int64_t n_blk, double* partial, double* out, hipStream_t s);
+// Krylov helpers.  launch_kdots: out[j] = <x, V + j nvec>_h for j < k
+// (deterministic: at most kDotGroups workgroups, fixed-order sums; partial
+// holds kDotGroups * k values); acc as in k_kdots_final.
+constexpr int kDotGroups = 1024;
+int kdot_groups(int64_t nvec);
+hipError_t launch_kdots(const double* x, const double* V, int64_t nvec, int k, const double* w, int n_loc,
+                        double* partial, double* out, double* acc, int accumulate, hipStream_t s);
+hipError_t launch_knormalize(double* v, int64_t n, const double* nn, double* hn, hipStream_t s);
+hipError_t launch_kapply(double* out, const double* v, const double* c, int64_t n, hipStream_t s);
 
 }  // namespace ihdg

@@ -75,40 +75,81 @@ __global__ void k_from_user(const double* __restrict__ us, double* __restrict__ 
 
 // Weighted inner products <x, y_j>_h for j < k over the interleaved layout:
 // one partial per (block, j), then a fixed-order sum per j.
-__global__ __launch_bounds__(256) void k_dots_partial(const double* __restrict__ x, const double* const* ys, int k,
-                                                      const double* __restrict__ w, int n_loc, int64_t n_blk,
-                                                      double* __restrict__ partial) {
-  __shared__ double red[4][16];
-  const int64_t blk = blockIdx.x;
+// Weighted inner products <x, V_j>_h for the basis vectors V_j = V + j * nvec,
+// j < k.  Grid (G, ceil(k / 8)): workgroup (g, c) takes products 8c .. 8c + 7
+// over the entries g * 256 + t, strided by G * 256 (G fixed by the vector
+// length, so the summation order is too), accumulating 8 sums per thread.
+// partial[g * k + j]: workgroup g's share, summed in a fixed order (entries of
+// a thread, lanes by the butterfly, then the 4 waves).
+__global__ __launch_bounds__(256) void k_kdots_partial(const double* __restrict__ x, const double* __restrict__ V,
+                                                       int64_t nvec, int k, const double* __restrict__ w, int n_loc,
+                                                       double* __restrict__ partial) {
+  __shared__ double red[4][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int j = 0; j < k; ++j) {
-    double s = 0.0;
-    for (int r = wv; r < n_loc; r += 4) {
-      int64_t o = (blk * n_loc + r) * kLanes + lane;
-      s += w[r] * x[o] * ys[j][o];
-    }
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) red[wv][j & 15] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blk * k + j] = red[0][j & 15] + red[1][j & 15] + red[2][j & 15] + red[3][j & 15];
-    __syncthreads();
+  const int j0 = blockIdx.y * 8;
+  const int kk = k - j0 < 8 ? k - j0 : 8;
+  double s[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) s[j] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < nvec; o += stride) {
+    const int r = (int)((o >> 6) % n_loc);  // [blk][row][lane] layout
+    const double xw = w[r] * x[o];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j < kk) s[j] += xw * V[(int64_t)(j0 + j) * nvec + o];
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    double t = s[j];
+    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (lane == 0) red[wv][j] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < kk) {
+    const int j = threadIdx.x;
+    partial[(int64_t)blockIdx.x * k + j0 + j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
   }
 }
-__global__ __launch_bounds__(256) void k_dots_final(const double* __restrict__ partial, int k, int64_t n_blk,
-                                                    double* out) {
+
+// out[j] = sum over the G workgroup partials of product j (one workgroup per j,
+// fixed-order tree).  acc (optional): acc[j] = out[j] (accumulate = 0) or
+// acc[j] += out[j] (accumulate = 1).
+__global__ __launch_bounds__(256) void k_kdots_final(const double* __restrict__ partial, int groups, int k,
+                                                     double* __restrict__ out, double* __restrict__ acc,
+                                                     int accumulate) {
   __shared__ double s[256];
-  for (int j = 0; j < k; ++j) {
-    double a = 0.0;
-    for (int64_t i = threadIdx.x; i < n_blk; i += 256) a += partial[i * k + j];
-    s[threadIdx.x] = a;
-    __syncthreads();
-    for (int w = 128; w >= 1; w >>= 1) {
-      if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[j] = s[0];
+  const int j = blockIdx.x;
+  double a = 0.0;
+  for (int g = threadIdx.x; g < groups; g += 256) a += partial[(int64_t)g * k + j];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
+  if (threadIdx.x == 0) {
+    out[j] = s[0];
+    if (acc) acc[j] = accumulate ? acc[j] + s[0] : s[0];
+  }
+}
+
+// v <- v / sqrt(nn) (nn on the device; v untouched if nn <= 0), and the norm
+// stored at *hn
+__global__ void k_knormalize(double* __restrict__ v, int64_t n, const double* __restrict__ nn, double* __restrict__ hn) {
+  const double h = sqrt(fmax(*nn, 0.0));
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hn = h;
+  if (!(h > 0.0)) return;
+  const double inv = 1.0 / h;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = inv * v[i];
+}
+
+// out <- (v - out) + c: the Krylov operator (I - T) v from the sweep psi(v) in out
+__global__ void k_kapply(double* __restrict__ out, const double* __restrict__ v, const double* __restrict__ c,
+                         int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (v[i] - out[i]) + c[i];
 }
 
 // w -= sum_j h[j] V_j, V_j = V + j * n (contiguous basis vectors), h on the device
@@ -221,11 +262,27 @@ hipError_t launch_reduce_batched(const BatchDesc* descs, int n, double* norms, h
   hipLaunchKernelGGL(k_reduce_batched, dim3((unsigned)n), dim3(256), 0, s, descs, norms);
   return hipGetLastError();
 }
-hipError_t launch_dots(const double* x, const double* const* ys, int k, const double* w, int n_loc, int64_t n_blk,
-                       double* partial, double* out, hipStream_t s) {
-  if (k > 16) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dots_partial, dim3((unsigned)n_blk), dim3(256), 0, s, x, ys, k, w, n_loc, n_blk, partial);
-  hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(256), 0, s, partial, k, n_blk, out);
+// about 4 entries per thread, at most kDotGroups workgroups
+int kdot_groups(int64_t nvec) {
+  const int64_t g = (nvec + 1023) / 1024;
+  return (int)(g < 1 ? 1 : (g > kDotGroups ? kDotGroups : g));
+}
+
+hipError_t launch_kdots(const double* x, const double* V, int64_t nvec, int k, const double* w, int n_loc,
+                        double* partial, double* out, double* acc, int accumulate, hipStream_t s) {
+  if (k <= 0 || nvec <= 0) return hipErrorInvalidValue;
+  const int g = kdot_groups(nvec);
+  hipLaunchKernelGGL(k_kdots_partial, dim3((unsigned)g, (unsigned)((k + 7) / 8)), dim3(256), 0, s, x, V, nvec, k, w,
+                     n_loc, partial);
+  hipLaunchKernelGGL(k_kdots_final, dim3((unsigned)k), dim3(256), 0, s, partial, g, k, out, acc, accumulate);
+  return hipGetLastError();
+}
+hipError_t launch_knormalize(double* v, int64_t n, const double* nn, double* hn, hipStream_t s) {
+  hipLaunchKernelGGL(k_knormalize, dim3(grid_for(n)), dim3(256), 0, s, v, n, nn, hn);
+  return hipGetLastError();
+}
+hipError_t launch_kapply(double* out, const double* v, const double* c, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_kapply, dim3(grid_for(n)), dim3(256), 0, s, out, v, c, n);
   return hipGetLastError();
 }
 
