@@ -66,7 +66,7 @@ def counter_traffic(key, waves):
     try:
         with open(os.path.join(ROOT, "profiles", "counters.json")) as f:
             d = json.load(f)[key]
-        with open(os.path.join(ROOT, "paper_1605_03228_amd", "csrc", "sweep_impl.hpp"), "rb") as f:
+        with open(os.path.join(ROOT, d.get("source", "paper_1605_03228_amd/csrc/sweep_impl.hpp")), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
         return d["traffic_bytes"] if (sha == d["source_sha16"] and waves == d["waves"]) else None
     except (OSError, KeyError, ValueError):
@@ -76,7 +76,12 @@ def counter_traffic(key, waves):
 KERNEL = {"cfg1": "k_sweep_mfma<double, transport, 2, 2>", "cfg2": "k_sweep<double, transport, 2, 4, per-element>",
           "cfg3": "k_sweep_mfma<double, transport, 3, 3>", "cfg4a": "k_sweep_mfma<double, shallow water, 2, 3>",
           "cfg4b": "k_sweep<double, conv.-diff., 2, 4, per-element>"}
-KEYS = {w: KERNEL[w] for w in ("cfg2", "cfg3", "cfg4b")}
+# the matrix-core transport kernel without LDS staging (launch shape 5)
+DIRECT = {"cfg1": "k_sweep_direct<double, 2, 2>", "cfg3": "k_sweep_direct<double, 3, 3>"}
+
+
+def kernel_name(workload, waves):
+    return DIRECT[workload] if (waves == 5 and workload in DIRECT) else KERNEL[workload]
 
 
 def make_problem(name):
@@ -284,10 +289,10 @@ def main():
                    "n_el": n_el, "n_loc": n_loc, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": counter_traffic(KEYS.get(args.workload), kw),
+                     "traffic": counter_traffic(kernel_name(args.workload, kw), kw),
                      "kernel_waves": kw,
                      "bytes_per_element": bpe64, "flops_per_element": flops_el, "achieved_tflops": tflops,
-                     "kernel": KERNEL[args.workload]},
+                     "kernel": kernel_name(args.workload, kw)},
         "fp64": {"setup_s": setup_s, "solve_tol": tol, "time_to_tol_s": ttt64, "sweeps": r64["iters"],
                  "status": r64["status"], "rel_err_vs_oracle": err64},
         "mixed": {"setup_s": setup_mx, "solve_tol": tol, "time_to_tol_s": tttmx,
