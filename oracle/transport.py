@@ -229,9 +229,12 @@ class TransportOperators:
             Jf = mesh.face_jac(fm)
             Mw = np.einsum("q,qb,qc->cb", Wf * Jf * np.abs(self.bn[em, fm]), Mu, Mu)
             add(k * nfp, k * nfp, -2.0 * Mw)
-        S = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                          shape=(nt, nt)).tocsc()
-        lam = spla.splu(S).solve(rhs)
+        if nt == 0:  # no interior faces: the local solves with boundary data are the solution
+            lam = np.zeros(0)
+        else:
+            S = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                              shape=(nt, nt)).tocsc()
+            lam = spla.splu(S).solve(rhs)
         u = np.zeros((ne, el.np))
         for e in range(ne):
             r = Fb[e].copy()

@@ -65,3 +65,21 @@ def test_footprint_shared_vs_per_element(lib):
     assert per > shared + 4096 * 25 * 20 * 8 * 0.9
     mixed, _ = b.footprint((64, 64), 4, b.TRANSPORT, None, prec=b.MIXED)
     assert mixed > per
+
+
+def test_mesh_limits(lib):
+    """Empty meshes are rejected as invalid arguments; meshes above 2^30
+    elements (the limit of the int32 face map times 64-element blocks) as
+    unsupported."""
+    from paper_1605_03228_amd import binding as b
+    for n in [(0, 5), (5, 0), (3, 0, 3)]:
+        with pytest.raises(b.IhdgError) as e:
+            b.sizes(n, 2, b.TRANSPORT)
+        assert e.value.status == 1, n
+    with pytest.raises(b.IhdgError) as e:
+        b.sizes((1 << 11, 1 << 11, 1 << 9), 1, b.TRANSPORT)  # 2^31 elements
+    assert e.value.status == 2
+    s = b.sizes((1 << 15, 1 << 15), 1, b.TRANSPORT)           # exactly 2^30 elements
+    assert s["n_el"] == 1 << 30
+    s = b.sizes((1, 1), 6, b.CD)
+    assert s["n_el"] == 1 and s["n_loc"] == 3 * 49 and s["n_in"] == 28

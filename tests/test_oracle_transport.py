@@ -253,3 +253,34 @@ def test_paper_table1_npc_2d_iteration_counts(n_el, p, iters):
         if np.sqrt(np.einsum("ei,ij,ej->", d, M, d)) < 1e-10:
             break
     assert abs(k - iters) <= 1, (k, iters)
+
+
+@pytest.mark.parametrize("n", [(1, 1), (1, 6), (7, 1), (1, 1, 1)])
+def test_degenerate_meshes_single_element_and_strips(n):
+    """Meshes without interior faces in some direction: the trace system is
+    empty (one element) or one-dimensional; direct, downwind and iHDG agree, and
+    a polynomial solution in Q^p is reproduced exactly."""
+    beta = (1.0, 0.5) if len(n) == 2 else (0.3, -0.5, 0.8)
+    pr = w.transport_poly(n, 2, beta, deg=2)
+    o = TransportOperators(pr)
+    u, k, _ = o.ihdg(tol=1e-14)
+    d = o.downwind()
+    ex = o.nodal(pr.exact)
+    assert np.abs(d - ex).max() < 1e-11
+    assert np.abs(u - d).max() < 1e-11
+    if len(n) == 2:
+        assert np.abs(o.direct_hdg() - d).max() < 1e-11
+
+
+@pytest.mark.parametrize("beta", [(1.0, 0.0), (0.0, -1.0)])
+def test_tangential_flow_faces(beta):
+    """beta . n = 0 on every face normal to one axis: those faces carry no flux
+    (weight 0 in the trace), and each row of elements is an independent 1-D
+    problem; iHDG still converges to the downwind solution and reproduces Q^p."""
+    pr = w.transport_poly((5, 4), 2, beta, deg=2)
+    o = TransportOperators(pr)
+    u, k, _ = o.ihdg(tol=1e-14)
+    d = o.downwind()
+    ex = o.nodal(pr.exact)
+    assert np.abs(d - ex).max() < 1e-11
+    assert np.abs(u - d).max() < 1e-11
