@@ -284,3 +284,73 @@ def test_tangential_flow_faces(beta):
     ex = o.nodal(pr.exact)
     assert np.abs(d - ex).max() < 1e-11
     assert np.abs(u - d).max() < 1e-11
+
+
+def test_per_sweep_element_flux_balance():
+    """One sweep from an arbitrary iterate satisfies, on every element, the
+    local equation tested with v = 1 (Section 3.1, the energy argument before
+    Theorem 1 uses the same test):
+
+        (sigma u^{k+1}, 1)_K - (u^{k+1}, div beta)_K + <2 (beta.n)^+ u^{k+1}, 1>_dK
+            = (f, 1)_K + <(beta.n)^+ u^k_own + (beta.n)^- u^k_ext, 1>_dK,
+
+    with u_ext = g on inflow boundary faces.  Checked with integrals written out
+    here from the nodal values (tensor Lagrange interpolation on the GLL nodes,
+    Gauss rules), independently of the oracle's assembled matrices; the f and g
+    terms use the discretisation's (p+2)-point rule, the polynomial terms are
+    exact for any rule of that size."""
+    from oracle.reference_element import gauss, gll, lagrange
+    n, p, beta, sig = (4, 3), 2, (0.8, -0.45), 0.7
+    pr = w.transport_const(n, p, beta, sigma=sig)
+    o = TransportOperators(pr)
+    rng = np.random.default_rng(7)
+    uk = rng.standard_normal((o.mesh.n_el, (p + 1) ** 2))
+    un = o.sweep(uk)
+    r, _ = gll(p)
+    q, wq = gauss(p + 2)
+    Lq = lagrange(r, q)[0]                          # [q, j] = l_j(q)
+    Le = lagrange(r, np.array([-1.0, 1.0]))[0]      # [side, j]
+    hx, hy = 1.0 / n[0], 1.0 / n[1]
+    bvec = np.array(beta)
+
+    def vol(uel):  # integral of the interpolant over the element
+        U = uel.reshape(p + 1, p + 1)  # [iy, ix]
+        return (hx * hy / 4) * np.einsum("a,b,aj,bi,ji->", wq, wq, Lq, Lq, U)
+
+    def face_vals(uel, f):  # interpolant at the Gauss points of local face f
+        U = uel.reshape(p + 1, p + 1)
+        ax, side = f // 2, f % 2
+        if ax == 0:
+            return Lq @ (U @ Le[side])            # along y at x = side
+        return (Le[side] @ U) @ Lq.T              # along x at y = side
+
+    def face_points(e, f):
+        i, j = e % n[0], e // n[0]
+        ax, side = f // 2, f % 2
+        x0, y0 = i * hx, j * hy
+        if ax == 0:
+            return np.stack([np.full(q.size, x0 + side * hx), y0 + hy / 2 * (q + 1)], -1), hy / 2
+        return np.stack([x0 + hx / 2 * (q + 1), np.full(q.size, y0 + side * hy)], -1), hx / 2
+
+    for e in range(o.mesh.n_el):
+        i, j = e % n[0], e // n[0]
+        xs = np.stack(np.meshgrid(i * hx + hx / 2 * (q + 1), j * hy + hy / 2 * (q + 1), indexing="xy"), -1)
+        fint = (hx * hy / 4) * np.einsum("a,b,ba->", wq, wq, pr.forcing(xs, sig)[..., 0])
+        lhs = sig * vol(un[e])
+        rhs = fint
+        for f in range(4):
+            ax, side = f // 2, f % 2
+            nrm = np.zeros(2)
+            nrm[ax] = 1.0 if side else -1.0
+            bn = float(bvec @ nrm)
+            pts, jf = face_points(e, f)
+            lhs += 2 * max(bn, 0.0) * jf * (wq @ face_vals(un[e], f))
+            own = face_vals(uk[e], f)
+            nb = [i - 1 if ax == 0 and side == 0 else i + 1 if ax == 0 else i,
+                  j - 1 if ax == 1 and side == 0 else j + 1 if ax == 1 else j]
+            if 0 <= nb[0] < n[0] and 0 <= nb[1] < n[1]:
+                ext = face_vals(uk[nb[0] + n[0] * nb[1]], f ^ 1)
+            else:
+                ext = pr.bdry(pts)[..., 0]
+            rhs += jf * (wq @ (max(bn, 0.0) * own + max(-bn, 0.0) * ext))
+        assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs) + 1.0), (e, lhs, rhs)
