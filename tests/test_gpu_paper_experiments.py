@@ -1,4 +1,5 @@
-"""The paper's transport experiments run on the GPU path (Section 5.1, Table 1).
+"""The paper's transport (Section 5.1, Table 1) and shallow-water (Section 5.2)
+experiments run on the GPU path.
 
 The 2-D discontinuous-solution test (beta = (1 + sin(pi y/2), 2) on [0,2]^2)
 is swept on the GPU one sweep at a time with the paper's stopping rule, an
@@ -61,3 +62,111 @@ def test_table1_npc_2d_on_gpu(n_el, p):
     k = count_sweeps(w.transport_e1(n, p), "npc")
     print(f"npc n_el={n_el} p={p}: gpu {k}, paper {NPC[(n_el, p)]}")
     assert abs(k - NPC[(n_el, p)]) <= 3
+
+
+GOLD_SW = os.path.join(os.path.dirname(__file__), "golden", "sw_iterations_per_step.txt")
+
+
+def _sw_rows():
+    rows = {}
+    for line in open(GOLD_SW):
+        if line.startswith("#") or not line.strip():
+            continue
+        n_el, p, k = (int(v) for v in line.split())
+        rows[(n_el, p)] = k
+    return rows
+
+
+def _sw_first_step_gpu(n, p):
+    from paper_1605_03228_amd.binding import node_points
+    from paper_1605_03228_amd.problem_io import make_solver
+    pr = w.sw_free_wave((n, n), p, (1.0 / n) / ((p + 1) * (p + 2)))
+    print(f"[gpu] {pr.name} first CN step", flush=True)
+    s = make_solver(pr, time_stepping=True, check_every=1)
+    x = node_points(pr.n, pr.p)
+    s.set_solution(pr.meta["exact_at"](0.0)(x, torch).permute(0, 2, 1).contiguous())
+    s.time_step("cn")
+    for k in range(1, 500):
+        inc, _ = s.sweep(1, norms=True)
+        if inc < 1e-10:
+            s.close()
+            return k
+    s.close()
+    return -1
+
+
+def _sw_first_step_oracle(n, p):
+    from oracle.norms import h_norm
+    from oracle.shallow_water import SWOperators
+    pr = w.sw_free_wave((n, n), p, (1.0 / n) / ((p + 1) * (p + 2)))
+    o = SWOperators(pr)
+    U = o.nodal(pr.meta["exact_at"](0.0))
+    o.F = o.cn_step_rhs(U)
+    for k in range(1, 500):
+        Un = o.sweep(U)
+        inc = h_norm(o.mesh, o.el, Un - U)
+        U = Un
+        if inc < 1e-10:
+            return k
+    return -1
+
+
+def test_sw_iterations_per_step_table_on_gpu():
+    """Section 5.2's shallow-water table (iterations per Crank-Nicolson step at
+    dt = h/((p+1)(p+2)), N_el = 16 .. 1024, p = 1 .. 4) on the GPU path: the
+    same count as the oracle's (within one) up to N_el = 256, within max(4, 35%)
+    of the printed counts, never growing with N at fixed p, smallest at p = 3."""
+    gold = _sw_rows()
+    got = {}
+    for n in (4, 8, 16, 32):
+        for p in (1, 2, 3, 4):
+            got[(n * n, p)] = _sw_first_step_gpu(n, p)
+            if n <= 16:
+                k_or = _sw_first_step_oracle(n, p)
+                assert abs(got[(n * n, p)] - k_or) <= 1, (n, p, got[(n * n, p)], k_or)
+    print("gpu:", got)
+    for key, k in got.items():
+        assert abs(k - gold[key]) <= max(4, 0.35 * gold[key]), (key, k, gold[key])
+    for p in (1, 2, 3, 4):
+        assert got[(16, p)] >= got[(64, p)] >= got[(256, p)] >= got[(1024, p)], p
+    for n_el in (16, 64, 256, 1024):
+        assert min(range(1, 5), key=lambda p: got[(n_el, p)]) == 3, n_el
+
+
+def _upwind_rows_3d():
+    rows = []
+    for line in open(GOLD):
+        if line.startswith("#") or not line.strip():
+            continue
+        d, n_el, p, it = (int(v) for v in line.split())
+        if d == 3 and n_el <= 512:
+            rows.append((n_el, p, it))
+    return rows
+
+
+@pytest.mark.parametrize("n_el,p,iters", _upwind_rows_3d())
+def test_table1_upwind_3d_on_gpu(n_el, p, iters):
+    """Table 1's 3-D smooth test (beta = (z, x, y)) on the GPU path with the
+    paper's stopping rule for it: the change of the exact L2 error between
+    sweeps below 1e-10 (error of each GPU iterate evaluated on the host)."""
+    from oracle.mesh import BoxMesh, TensorElement
+    from oracle.norms import l2_error
+    from paper_1605_03228_amd.problem_io import make_solver
+    n = int(round(n_el ** (1 / 3)))
+    pr = w.transport_e2(n, p)
+    print(f"[gpu] {pr.name} 3-D Table 1", flush=True)
+    s = make_solver(pr)
+    mesh = BoxMesh(pr.n, pr.lo, pr.hi)
+    el = TensorElement(pr.dim, pr.p)
+    prev = None
+    for k in range(1, 2000):
+        s.sweep(1)
+        u = s.get_solution()
+        torch.cuda.synchronize()
+        e = l2_error(mesh, el, u.reshape(u.shape[0], -1).cpu().numpy(), lambda x: pr.exact(x)[..., 0])
+        if prev is not None and abs(e - prev) < 1e-10:
+            break
+        prev = e
+    s.close()
+    print(f"3-D n_el={n_el} p={p}: gpu {k}, paper {iters}")
+    assert abs(k - iters) <= 0.1 * iters + 1, (k, iters)

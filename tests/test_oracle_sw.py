@@ -1,4 +1,6 @@
 """Pins on the linearised shallow-water oracle (Section 3 and Section 5.2)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -101,3 +103,50 @@ def test_crank_nicolson_is_second_order_in_time():
                         for c in range(3)))
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates > 1.9), rates
+
+
+GOLD_SW = os.path.join(os.path.dirname(__file__), "golden", "sw_iterations_per_step.txt")
+
+
+def _sw_table():
+    t = {}
+    for line in open(GOLD_SW):
+        if line.startswith("#") or not line.strip():
+            continue
+        n_el, p, k = (int(v) for v in line.split())
+        t[(n_el, p)] = k
+    return t
+
+
+def first_step_iterations(n, p):
+    """Iterations of the first Crank-Nicolson step of the standing wave from its
+    initial state (warm start = that state), stopping on an absolute h-norm
+    increment below 1e-10."""
+    pr = w.sw_free_wave((n, n), p, (1.0 / n) / ((p + 1) * (p + 2)))
+    o = SWOperators(pr)
+    U = o.nodal(pr.meta["exact_at"](0.0))
+    o.F = o.cn_step_rhs(U)
+    for k in range(1, 500):
+        Un = o.sweep(U)
+        inc = h_norm(o.mesh, o.el, Un - U)
+        U = Un
+        if inc < 1e-10:
+            return k
+    return -1
+
+
+def test_paper_sw_iterations_per_step():
+    """Section 5.2's table of iterations per step at dt = h/((p+1)(p+2)), for
+    N_el = 16, 64, 256: within max(4, 35%) of the printed counts, never growing
+    with N at fixed p, and smallest at p = 3 on every mesh."""
+    gold = _sw_table()
+    got = {}
+    for n in (4, 8, 16):
+        for p in (1, 2, 3, 4):
+            got[(n * n, p)] = first_step_iterations(n, p)
+    for key, k in got.items():
+        assert abs(k - gold[key]) <= max(4, 0.35 * gold[key]), (key, k, gold[key])
+    for p in (1, 2, 3, 4):
+        assert got[(16, p)] >= got[(64, p)] >= got[(256, p)], p
+    for n_el in (16, 64, 256):
+        assert min(range(1, 5), key=lambda p: got[(n_el, p)]) == 3, n_el
