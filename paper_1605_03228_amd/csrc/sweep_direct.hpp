@@ -243,15 +243,23 @@ __global__ __launch_bounds__(256) void k_sweep_direct_batched(const BatchDesc* _
   if (tid == 0) direct_partials(a.partials, blk, red);
 }
 
-// Resident workgroups per CU as the swizzled operator's LDS admits them (at
-// most 8), times 256 CUs, with the blocks spread evenly over the persistent
-// grid.
+// Workgroups of the persistent kernel that are resident at once (the
+// runtime's occupancy for its registers and LDS, times the CUs; queried once
+// per instance), with the blocks spread evenly over them.
 template <typename T, int DIM, int P>
 inline int64_t direct_grid(int64_t n_blk) {
-  constexpr int64_t per_cu = (160 * 1024) / (DirectShape<T, DIM, P>::LDS * (int64_t)sizeof(T) + 128);
-  constexpr int64_t kResident = 256 * (per_cu < 1 ? 1 : (per_cu > 8 ? 8 : per_cu));
-  if (n_blk <= kResident) return n_blk;
-  const int64_t per = (n_blk + kResident - 1) / kResident;
+  static const int64_t resident = [] {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_direct<T, DIM, P>, 256, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 256;
+    return (int64_t)per_cu * cus;
+  }();
+  if (n_blk <= resident) return n_blk;
+  const int64_t per = (n_blk + resident - 1) / resident;
   return (n_blk + per - 1) / per;
 }
 
