@@ -5,8 +5,13 @@ element (relative h-norm over the whole mesh) with the oracle's own solution of
 the same discrete problem: downwind block substitution for transport, the
 assembled HDG trace system for shallow water and convection-diffusion.  FP64
 runs to a relative increment of 1e-12 must agree to 1e-10; mixed-precision
-runs to a relative FP64 defect of 1e-10 must agree to 1e-8.
+runs to a relative FP64 defect of 1e-10 must agree to 1e-8.  Both the
+GLL-weighted h-norm (the norm of the stopping rule) and the true L2(Omega)
+norm, evaluated with a (p+3)-point Gauss rule that integrates the squared
+interpolants exactly, are checked.
 """
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -29,6 +34,24 @@ def reference(name, make):
         ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
         _REF[name] = (pr, o, ref)
     return _REF[name]
+
+
+def l2_rel(o, a, b):
+    """||a - b||_L2 / ||b||_L2 over all fields of nodal fields a, b (uniform
+    mesh: the Jacobian cancels)."""
+    from oracle.reference_element import gauss, lagrange
+    el, mesh = o.el, o.mesh
+    xq, wq = gauss(el.p + 3)
+    L, _ = lagrange(el.r1, xq)
+    qm = [tuple(reversed(t)) for t in itertools.product(range(len(xq)), repeat=mesh.dim)]
+    B = np.array([[np.prod([L[q[d], im[d]] for d in range(mesh.dim)]) for im in el.node_multi] for q in qm])
+    W = np.array([np.prod([wq[q[d]] for d in range(mesh.dim)]) for q in qm])
+
+    def sq(v):
+        v = np.asarray(v).reshape(mesh.n_el, -1, el.np)
+        return float(np.einsum("q,efq->", W, (v @ B.T) ** 2))
+
+    return np.sqrt(sq(np.asarray(a) - np.asarray(b)) / sq(b))
 
 
 def run(pr, tol, **kw):
@@ -58,8 +81,9 @@ def test_fullsize_fp64(name, make):
     res, u = run(pr, 1e-12)
     assert res["status"] == 0, res
     err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
-    print(f"{name} fp64: {res['iters']} sweeps, rel err {err:.3e}")
-    assert err < 1e-10
+    el2 = l2_rel(o, u, ref)
+    print(f"{name} fp64: {res['iters']} sweeps, rel err {err:.3e} (h-norm), {el2:.3e} (L2)")
+    assert err < 1e-10 and el2 < 1e-10
 
 
 @pytest.mark.parametrize("name,make", CONFIGS, ids=[c[0] for c in CONFIGS])
@@ -68,8 +92,10 @@ def test_fullsize_mixed(name, make):
     res, u = run(pr, 1e-10, prec=1)
     assert res["status"] == 0, res
     err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
-    print(f"{name} mixed: {res['fp32_sweeps']} fp32 + {res['fp64_sweeps']} fp64 sweeps, rel err {err:.3e}")
-    assert err < 1e-8
+    el2 = l2_rel(o, u, ref)
+    print(f"{name} mixed: {res['fp32_sweeps']} fp32 + {res['fp64_sweeps']} fp64 sweeps, rel err {err:.3e} (h-norm), "
+          f"{el2:.3e} (L2)")
+    assert err < 1e-8 and el2 < 1e-8
 
 
 def test_fullsize_cd_eps1e2_gmres():
@@ -79,5 +105,6 @@ def test_fullsize_cd_eps1e2_gmres():
     res, u = run(pr, 1e-12, krylov_restart=100, max_iters=20000)
     assert res["status"] == 0, res
     err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
-    print(f"cfg4b eps=1e-2 gmres: {res['krylov_iters']} iterations, rel err {err:.3e}")
-    assert err < 1e-9
+    el2 = l2_rel(o, u, ref)
+    print(f"cfg4b eps=1e-2 gmres: {res['krylov_iters']} iterations, rel err {err:.3e} (h-norm), {el2:.3e} (L2)")
+    assert err < 1e-9 and el2 < 1e-9
