@@ -341,6 +341,23 @@ def main():
         if t32 > 0:
             fp32_rate = n_el * n_loc * rmx["fp32_sweeps"] / t32
 
+    # ---- transport: the NPC flux (same discrete solution, exact after as many
+    # sweeps as the mesh has flow layers) against the plain upwind FP64 solve
+    npc = None
+    if pr.pde == "transport" and args.flux == "upwind":
+        npc = {}
+        for key, prec in (("fp64", 0), ("mixed", 1)):
+            sn = make_solver(pr, device=dev, prec=prec, block_waves=args.waves, flux="npc")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rn = sn.solve(tol)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            npc[key] = {"time_to_tol_s": dt, "status": rn["status"], "u": sn.get_solution(),
+                        "speedup_vs_upwind_fp64": ttt64 / dt if dt > 0 else None,
+                        "sweeps": (rn["iters"] if prec == 0 else rn["fp32_sweeps"] + rn["fp64_sweeps"])}
+            sn.close()
+
     err64 = errmx = None
     cpu = None
     if not args.no_oracle:
@@ -355,6 +372,9 @@ def main():
         nr = h_norm(o.mesh, o.el, ref)
         err64 = h_norm(o.mesh, o.el, a64 - ref) / nr
         errmx = h_norm(o.mesh, o.el, amx - ref) / nr
+        for leg in (npc or {}).values():
+            un = leg["u"].reshape(n_el, -1).cpu().numpy()
+            leg["rel_err_vs_oracle"] = h_norm(o.mesh, o.el, un - ref) / nr
         if args.workload == "cfg2":
             cpu = cpu_baseline(pr)
 
@@ -387,6 +407,7 @@ def main():
                   "outer_steps": rmx["outer_steps"], "status": rmx["status"],
                   "fp32_sweep_rate": fp32_rate, "rel_err_vs_oracle": errmx,
                   "speedup_time_to_tol_vs_fp64": (ttt64 / tttmx) if tttmx > 0 else None},
+        "npc_flux": ({k: {kk: vv for kk, vv in v.items() if kk != "u"} for k, v in npc.items()} if npc else None),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
