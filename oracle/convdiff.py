@@ -234,3 +234,141 @@ class CDOperators:
 
     def nodal(self, fn):
         return np.array([fn(self.el.node_points(self.mesh, e)).T.reshape(-1) for e in range(self.mesh.n_el)])
+
+
+# -------------------------------------------------------------------------
+# dense brute force in a modal (Legendre) basis, volume + trace unknowns
+# -------------------------------------------------------------------------
+def brute_force_dense(prob, nq1=None):
+    """Assemble the whole HDG system densely and solve it.
+
+    Plain loops over elements, faces and quadrature points, a tensor Legendre
+    (modal) basis for (s_1, .., s_d, u) and for uhat, which is an explicit
+    unknown on every face.  Element rows: the two local equations of the
+    module docstring with uhat unknown.  Face rows, tested against Q^p(e): on
+    an interior face the jump of the normal flux s.n + beta.n u + tau (u - uhat)
+    vanishes (conservation); on a boundary face uhat = g.  A (p+4)-point Gauss
+    rule throughout, tau = (alpha - beta.n) / 2, alpha = sqrt((beta.n)^2 + 4).
+
+    Returns u_h(e, field, r_ref) -> value (field d = u).  Meant for meshes of
+    2-4 elements.
+    """
+    import itertools
+    from numpy.polynomial import legendre as Lg
+
+    mesh = BoxMesh(prob.n, prob.lo, prob.hi)
+    dim, p = mesh.dim, prob.p
+    m = dim + 1
+    nq1 = p + 4 if nq1 is None else nq1
+    xg, wg = Lg.leggauss(nq1)
+    vmodes = [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=dim)]
+    fmodes = [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=dim - 1)]
+    nv, nt = len(vmodes), len(fmodes)
+    kinv, nu = 1.0 / prob.kappa, prob.nu
+
+    def P(k, x):
+        co = np.zeros(k + 1); co[k] = 1.0
+        return Lg.legval(x, co)
+
+    def dP(k, x):
+        co = np.zeros(k + 1); co[k] = 1.0
+        return Lg.legval(x, Lg.legder(co))
+
+    def phi(mode, r):
+        return np.prod([P(mode[a], r[a]) for a in range(dim)])
+
+    def grad_phi(mode, r):
+        g = []
+        for a in range(dim):
+            t = dP(mode[a], r[a]) * 2.0 / mesh.h[a]
+            for b in range(dim):
+                if b != a:
+                    t *= P(mode[b], r[b])
+            g.append(t)
+        return np.array(g)
+
+    skel = mesh.skeleton()
+    face_of = {}
+    for k, (em, fm, ep, fp) in enumerate(skel):
+        face_of[(em, fm)] = k
+        if ep >= 0:
+            face_of[(ep, fp)] = k
+    nvol = mesh.n_el * m * nv
+    N = nvol + len(skel) * nt
+    M = np.zeros((N, N))
+    rhs = np.zeros(N)
+    J = mesh.jac()
+    col = lambda e, fld, j: e * m * nv + fld * nv + j
+    qpts = list(itertools.product(range(nq1), repeat=dim))
+    for e in range(mesh.n_el):
+        x0 = mesh.el_origin(e)
+        for qi in qpts:
+            r = np.array([xg[qi[a]] for a in range(dim)])
+            wq = np.prod([wg[qi[a]] for a in range(dim)]) * J
+            x = x0 + mesh.h / 2 * (r + 1)
+            b = prob.beta_at(x[None])[0]
+            db = prob.div_beta_at(x[None])[0]
+            fv = prob.forcing(x[None])[0, 0]
+            for i, mi in enumerate(vmodes):
+                vi = phi(mi, r)
+                gv = grad_phi(mi, r)
+                rhs[col(e, dim, i)] += wq * fv * vi
+                for j, mj in enumerate(vmodes):
+                    uj = phi(mj, r)
+                    for a in range(dim):
+                        # kappa^-1 (s_a, t) - (u, d_a t)   [t = v e_a]
+                        M[col(e, a, i), col(e, a, j)] += wq * kinv * uj * vi
+                        M[col(e, a, i), col(e, dim, j)] -= wq * uj * gv[a]
+                        # -(s_a, d_a v)
+                        M[col(e, dim, i), col(e, a, j)] -= wq * uj * gv[a]
+                    # -(u, beta . grad v + (div beta) v) + nu (u, v)
+                    M[col(e, dim, i), col(e, dim, j)] += wq * (-uj * (b @ gv + db * vi) + nu * uj * vi)
+        for f in range(2 * dim):
+            a, s = divmod(f, 2)
+            tang = [cx for cx in range(dim) if cx != a]
+            nvec = mesh.normal(f)
+            Jf = mesh.face_jac(f)
+            k = face_of[(e, f)]
+            interior = skel[k][2] >= 0
+            for qt in itertools.product(range(nq1), repeat=dim - 1):
+                r = np.zeros(dim)
+                r[a] = 1.0 if s == 1 else -1.0
+                for t, cx in enumerate(tang):
+                    r[cx] = xg[qt[t]]
+                wq = (np.prod([wg[q] for q in qt]) if dim > 1 else 1.0) * Jf
+                x = x0 + mesh.h / 2 * (r + 1)
+                bn = prob.beta_at(x[None])[0] @ nvec
+                tau = 0.5 * (np.sqrt(bn * bn + 4.0) - bn)
+                rt = [r[cx] for cx in tang]
+                mus = [np.prod([P(fm[t], rt[t]) for t in range(dim - 1)]) if dim > 1 else 1.0 for fm in fmodes]
+                for i, mi in enumerate(vmodes):
+                    vi = phi(mi, r)
+                    for cm, mu in enumerate(mus):
+                        # <uhat, t . n> in the s_a equation (t = v e_a: t . n = v n_a)
+                        M[col(e, a, i), nvol + k * nt + cm] += wq * nvec[a] * mu * vi
+                        # -<tau uhat, v> in the u equation
+                        M[col(e, dim, i), nvol + k * nt + cm] -= wq * tau * mu * vi
+                    for j, mj in enumerate(vmodes):
+                        uj = phi(mj, r)
+                        # <s . n + beta.n u + tau u, v>
+                        M[col(e, dim, i), col(e, a, j)] += wq * nvec[a] * uj * vi
+                        M[col(e, dim, i), col(e, dim, j)] += wq * (bn + tau) * uj * vi
+                for cm, muc in enumerate(mus):
+                    row = nvol + k * nt + cm
+                    if interior:
+                        # this side's share of the flux jump: <s.n + beta.n u + tau (u - uhat), mu>
+                        for j, mj in enumerate(vmodes):
+                            uj = phi(mj, r)
+                            M[row, col(e, a, j)] += wq * nvec[a] * uj * muc
+                            M[row, col(e, dim, j)] += wq * (bn + tau) * uj * muc
+                        for c2, mu2 in enumerate(mus):
+                            M[row, nvol + k * nt + c2] -= wq * tau * mu2 * muc
+                    else:
+                        for c2, mu2 in enumerate(mus):
+                            M[row, nvol + k * nt + c2] += wq * mu2 * muc
+                        rhs[row] += wq * prob.bdry(x[None])[0, 0] * muc
+    sol = np.linalg.solve(M, rhs)
+
+    def u_h(e, fld, r):
+        return sum(sol[col(e, fld, j)] * phi(mj, r) for j, mj in enumerate(vmodes))
+    return u_h

@@ -215,3 +215,127 @@ class SWOperators:
 
     def nodal(self, fn):
         return np.array([fn(self.el.node_points(self.mesh, e)).T.reshape(-1) for e in range(self.mesh.n_el)])
+
+
+# -------------------------------------------------------------------------
+# dense brute force in a modal (Legendre) basis, volume + trace unknowns
+# -------------------------------------------------------------------------
+def brute_force_dense(prob, nq1=None):
+    """Assemble the whole HDG system of one implicit step densely and solve it.
+
+    Plain loops over elements, faces and quadrature points, a tensor Legendre
+    (modal) basis for (phi, u, v) and for phihat, which is an explicit unknown
+    on every face.  Element rows: the three local equations of the module
+    docstring with phihat unknown.  Face rows, tested against Q^p(e): on an
+    interior face the normal mass flux Phi vel.n + sqrt(Phi)(phi - phihat)
+    summed over the two sides vanishes (conservation); on a wall it vanishes
+    on the one side.  A (p+4)-point Gauss rule throughout.
+
+    Returns u_h(e, field, r_ref) -> value.  Meant for meshes of 2-4 elements.
+    """
+    import itertools
+    from numpy.polynomial import legendre as Lg
+
+    mesh = BoxMesh(prob.n, prob.lo, prob.hi)
+    dim, p = 2, prob.p
+    nq1 = p + 4 if nq1 is None else nq1
+    xg, wg = Lg.leggauss(nq1)
+    vmodes = [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=dim)]
+    nv, nt = len(vmodes), p + 1
+    Phi, f0, gam = prob.Phi, prob.f0, prob.gamma
+    sP = np.sqrt(Phi)
+    c = prob.a_mass / prob.dt
+
+    def P(k, x):
+        co = np.zeros(k + 1); co[k] = 1.0
+        return Lg.legval(x, co)
+
+    def dP(k, x):
+        co = np.zeros(k + 1); co[k] = 1.0
+        return Lg.legval(x, Lg.legder(co))
+
+    def phi(mode, r):
+        return P(mode[0], r[0]) * P(mode[1], r[1])
+
+    def grad_phi(mode, r):
+        return np.array([dP(mode[0], r[0]) * 2.0 / mesh.h[0] * P(mode[1], r[1]),
+                         P(mode[0], r[0]) * dP(mode[1], r[1]) * 2.0 / mesh.h[1]])
+
+    skel = mesh.skeleton()
+    face_of = {}
+    for k, (em, fm, ep, fp) in enumerate(skel):
+        face_of[(em, fm)] = k
+        if ep >= 0:
+            face_of[(ep, fp)] = k
+    nvol = mesh.n_el * 3 * nv
+    N = nvol + len(skel) * nt
+    M = np.zeros((N, N))
+    rhs = np.zeros(N)
+    J = mesh.jac()
+    col = lambda e, fld, j: e * 3 * nv + fld * nv + j          # fld: 0 phi, 1 u, 2 v
+    for e in range(mesh.n_el):
+        x0 = mesh.el_origin(e)
+        for qa in range(nq1):
+            for qb in range(nq1):
+                r = np.array([xg[qa], xg[qb]])
+                wq = wg[qa] * wg[qb] * J
+                x = x0 + mesh.h / 2 * (r + 1)
+                Fv = prob.forcing(x[None])[0]
+                for i, mi in enumerate(vmodes):
+                    wi = phi(mi, r)
+                    gw = grad_phi(mi, r)
+                    for fld in range(3):
+                        rhs[col(e, fld, i)] += wq * Fv[fld] * wi
+                    for j, mj in enumerate(vmodes):
+                        uj = phi(mj, r)
+                        # phi equation: c (phi, w) - Phi (vel, grad w)
+                        M[col(e, 0, i), col(e, 0, j)] += wq * c * uj * wi
+                        M[col(e, 0, i), col(e, 1, j)] -= wq * Phi * uj * gw[0]
+                        M[col(e, 0, i), col(e, 2, j)] -= wq * Phi * uj * gw[1]
+                        # u equation: (c + gamma) Phi (u, w) - f0 Phi (v, w) - Phi (phi, d_x w)
+                        M[col(e, 1, i), col(e, 1, j)] += wq * (c + gam) * Phi * uj * wi
+                        M[col(e, 1, i), col(e, 2, j)] -= wq * f0 * Phi * uj * wi
+                        M[col(e, 1, i), col(e, 0, j)] -= wq * Phi * uj * gw[0]
+                        # v equation: (c + gamma) Phi (v, w) + f0 Phi (u, w) - Phi (phi, d_y w)
+                        M[col(e, 2, i), col(e, 2, j)] += wq * (c + gam) * Phi * uj * wi
+                        M[col(e, 2, i), col(e, 1, j)] += wq * f0 * Phi * uj * wi
+                        M[col(e, 2, i), col(e, 0, j)] -= wq * Phi * uj * gw[1]
+        for f in range(4):
+            a, s = divmod(f, 2)
+            t_ax = 1 - a
+            nvec = mesh.normal(f)
+            Jf = mesh.face_jac(f)
+            k = face_of[(e, f)]
+            for qt in range(nq1):
+                r = np.zeros(2)
+                r[a] = 1.0 if s == 1 else -1.0
+                r[t_ax] = xg[qt]
+                wq = wg[qt] * Jf
+                mus = [P(cm, xg[qt]) for cm in range(nt)]
+                for i, mi in enumerate(vmodes):
+                    wi = phi(mi, r)
+                    for j, mj in enumerate(vmodes):
+                        uj = phi(mj, r)
+                        # <Phi vel.n + sqrt(Phi) phi, w> in the phi equation
+                        M[col(e, 0, i), col(e, 0, j)] += wq * sP * uj * wi
+                        M[col(e, 0, i), col(e, 1, j)] += wq * Phi * nvec[0] * uj * wi
+                        M[col(e, 0, i), col(e, 2, j)] += wq * Phi * nvec[1] * uj * wi
+                    for cm, mu in enumerate(mus):
+                        M[col(e, 0, i), nvol + k * nt + cm] -= wq * sP * mu * wi
+                        M[col(e, 1, i), nvol + k * nt + cm] += wq * Phi * nvec[0] * mu * wi
+                        M[col(e, 2, i), nvol + k * nt + cm] += wq * Phi * nvec[1] * mu * wi
+                # this side's share of the face row: <Phi vel.n + sqrt(Phi)(phi - phihat), mu>
+                for cm, muc in enumerate(mus):
+                    row = nvol + k * nt + cm
+                    for j, mj in enumerate(vmodes):
+                        uj = phi(mj, r)
+                        M[row, col(e, 0, j)] += wq * sP * uj * muc
+                        M[row, col(e, 1, j)] += wq * Phi * nvec[0] * uj * muc
+                        M[row, col(e, 2, j)] += wq * Phi * nvec[1] * uj * muc
+                    for c2, mu2 in enumerate(mus):
+                        M[row, nvol + k * nt + c2] -= wq * sP * mu2 * muc
+    sol = np.linalg.solve(M, rhs)
+
+    def u_h(e, fld, r):
+        return sum(sol[col(e, fld, j)] * phi(mj, r) for j, mj in enumerate(vmodes))
+    return u_h

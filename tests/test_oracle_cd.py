@@ -84,3 +84,18 @@ def test_gmres_recovers_direct_where_ihdg_diverges():
     x, info, it = o.gmres(tol=1e-12)
     assert info == 0
     assert rel(o, x, o.direct_hdg()) < 1e-10
+
+
+@pytest.mark.parametrize("n,p,kappa", [((2, 1), 1, 0.7), ((2, 2), 1, 0.05), ((1, 2), 2, 1e-3)])
+def test_brute_force_modal_dense(n, p, kappa):
+    """Dense volume+trace solve in a Legendre basis with a (p+4)-point rule
+    (polynomial data, constant beta so both rules integrate exactly) = the
+    condensed direct solve, on 2-4 elements."""
+    from oracle.convdiff import brute_force_dense
+    pr = w.cd_poly(n, p, kappa=kappa, affine_beta=False)
+    o = CDOperators(pr)
+    ud = o.direct_hdg()
+    uh = brute_force_dense(pr)
+    rn = [np.array([o.el.r1[im[a]] for a in range(2)]) for im in o.el.node_multi]
+    ub = np.array([[uh(e, fld, r) for fld in range(3) for r in rn] for e in range(o.mesh.n_el)])
+    assert np.abs(ub - ud).max() < 1e-11 * max(1.0, np.abs(ud).max())

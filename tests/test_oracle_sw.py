@@ -150,3 +150,20 @@ def test_paper_sw_iterations_per_step():
         assert got[(16, p)] >= got[(64, p)] >= got[(256, p)], p
     for n_el in (16, 64, 256):
         assert min(range(1, 5), key=lambda p: got[(n_el, p)]) == 3, n_el
+
+
+@pytest.mark.parametrize("n,p", [((2, 1), 1), ((2, 2), 1), ((1, 2), 2)])
+def test_brute_force_modal_dense(n, p):
+    """Dense volume+trace solve in a Legendre basis with a (p+4)-point rule
+    (polynomial data, so both rules integrate exactly) = the condensed direct
+    solve = the converged iteration, on 2-4 elements."""
+    from oracle.shallow_water import brute_force_dense
+    pr = w.sw_poly(n, p)
+    o = SWOperators(pr)
+    ud = o.direct_hdg()
+    uh = brute_force_dense(pr)
+    rn = [np.array([o.el.r1[im[a]] for a in range(2)]) for im in o.el.node_multi]
+    ub = np.array([[uh(e, fld, r) for fld in range(3) for r in rn] for e in range(o.mesh.n_el)])
+    assert np.abs(ub - ud).max() < 1e-11 * max(1.0, np.abs(ud).max())
+    u, _, _ = o.ihdg(tol=1e-14)
+    assert np.abs(u - ud).max() < 1e-10 * max(1.0, np.abs(ud).max())
