@@ -305,6 +305,12 @@ ihdg_status ihdg_batch_add(ihdg_batch* b, ihdg_ctx* ctx, double tol, int64_t tag
 ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active);
 /* Results of members that finished since the last poll (at most max_out). */
 ihdg_status ihdg_batch_poll(ihdg_batch* b, ihdg_batch_result* out, int32_t max_out, int32_t* n_out);
+/* Rounds replay a HIP graph of their launches (all groups' sweeps and the norm
+ * reduction), captured when the round's structure (groups, their block counts,
+ * sweeps per round) differs from the previous round's and replayed while it is
+ * the same; 1 by default on a non-null stream.  enable = 0: launch directly.
+ * The results are the same either way. */
+ihdg_status ihdg_batch_use_graphs(ihdg_batch* b, int32_t enable);
 void ihdg_batch_destroy(ihdg_batch* b);
 
 const char* ihdg_last_error(const ihdg_ctx* ctx);

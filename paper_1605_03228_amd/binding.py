@@ -67,7 +67,7 @@ EXPORTS = ["ihdg_sizes", "ihdg_quadrature_points", "ihdg_footprint", "ihdg_setup
            "ihdg_solve", "ihdg_residual", "ihdg_get_solution", "ihdg_set_solution", "ihdg_set_stream",
            "ihdg_get_stats", "ihdg_last_error", "ihdg_status_string", "ihdg_destroy",
            "ihdg_batch_footprint", "ihdg_batch_create", "ihdg_batch_add", "ihdg_batch_round",
-           "ihdg_batch_poll", "ihdg_batch_destroy", "ihdg_time_step", "ihdg_node_points"]
+           "ihdg_batch_poll", "ihdg_batch_use_graphs", "ihdg_batch_destroy", "ihdg_time_step", "ihdg_node_points"]
 
 
 def load():
@@ -104,6 +104,7 @@ def load():
     lib.ihdg_batch_add.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_int64]
     lib.ihdg_batch_round.argtypes = [C.c_void_p, C.c_int32, P(C.c_int32)]
     lib.ihdg_batch_poll.argtypes = [C.c_void_p, P(BatchResult), C.c_int32, P(C.c_int32)]
+    lib.ihdg_batch_use_graphs.argtypes = [C.c_void_p, C.c_int32]
     lib.ihdg_time_step.argtypes = [C.c_void_p, C.c_int32]
     lib.ihdg_node_points.argtypes = [P(Mesh), C.c_int32, C.c_void_p, C.c_void_p]
     lib.ihdg_batch_destroy.argtypes = [C.c_void_p]
@@ -291,7 +292,7 @@ class Batch:
     with one launch per group of same-shaped members, finished members are
     reported by poll()."""
 
-    def __init__(self, max_members=256, max_blocks=1 << 20, device="cuda"):
+    def __init__(self, max_members=256, max_blocks=1 << 20, device="cuda", use_graphs=True):
         lib = load()
         self.lib, self.device = lib, torch.device(device)
         nb = C.c_size_t()
@@ -302,6 +303,7 @@ class Batch:
         _check(lib.ihdg_batch_create(max_members, max_blocks, C.c_void_p(self.workspace.data_ptr()), nb.value,
                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
+        _check(lib.ihdg_batch_use_graphs(h, 1 if use_graphs else 0))
         self.members = {}
         self.max_members = max_members
 

@@ -1022,6 +1022,11 @@ struct ihdg_batch {
   std::vector<BMember> active;
   std::vector<ihdg_batch_result> done;
   std::string err;
+  // the launches of one round (every group's sweeps and the norm reduction),
+  // captured once per round structure and replayed while it is unchanged
+  bool use_graphs = true;
+  hipGraphExec_t graph = nullptr;
+  std::vector<int64_t> graph_sig;
 };
 
 static size_t batch_bytes(int32_t mm, int64_t mb, size_t* off_owner, size_t* off_norms) {
@@ -1074,7 +1079,17 @@ ihdg_status ihdg_batch_create(int32_t max_members, int64_t max_blocks, void* wor
   return IHDG_OK;
 }
 
-void ihdg_batch_destroy(ihdg_batch* b) { delete b; }
+void ihdg_batch_destroy(ihdg_batch* b) {
+  if (!b) return;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  delete b;
+}
+
+ihdg_status ihdg_batch_use_graphs(ihdg_batch* b, int32_t enable) {
+  if (!b) return IHDG_ERR_ARG;
+  b->use_graphs = enable != 0;
+  return IHDG_OK;
+}
 
 ihdg_status ihdg_batch_add(ihdg_batch* b, ihdg_ctx* c, double tol, int64_t tag) {
   if (!b || !c || !(tol > 0)) return IHDG_ERR_ARG;
@@ -1173,15 +1188,51 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
   if (hipMemcpyAsync(b->descs, hd.data(), hd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(b->owner, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
     return IHDG_ERR_HIP;
-  for (int s = 0; s < S; ++s) {
-    for (const G& g : gl) {
-      const bool single = std::get<5>(g.k) != 0;
-      if (single && s > 0) continue;
-      const bool fp32 = std::get<4>(g.k) != 0;
-      if (launch_batched(g.rep, fp32, b->descs + g.d0, b->owner + g.o0, g.nb, s, st) != hipSuccess) return IHDG_ERR_HIP;
+  auto enqueue = [&]() -> hipError_t {
+    for (int s = 0; s < S; ++s) {
+      for (const G& g : gl) {
+        const bool single = std::get<5>(g.k) != 0;
+        if (single && s > 0) continue;
+        const bool fp32 = std::get<4>(g.k) != 0;
+        hipError_t e = launch_batched(g.rep, fp32, b->descs + g.d0, b->owner + g.o0, g.nb, s, st);
+        if (e != hipSuccess) return e;
+      }
     }
+    return launch_reduce_batched(b->descs, (int)hd.size(), b->norms, st);
+  };
+  if (b->use_graphs && st != nullptr) {
+    // the round's structure: every launch parameter except the descriptor
+    // contents, which were copied to fixed device addresses above
+    std::vector<int64_t> sig{S, (int64_t)hd.size()};
+    for (const G& g : gl) {
+      const Key& k = g.k;
+      for (int64_t v : {(int64_t)std::get<0>(k), (int64_t)std::get<1>(k), (int64_t)std::get<2>(k),
+                        (int64_t)std::get<3>(k), (int64_t)std::get<4>(k), (int64_t)std::get<5>(k),
+                        (int64_t)std::get<6>(k), (int64_t)g.d0, g.o0, g.nb})
+        sig.push_back(v);
+    }
+    if (!b->graph || sig != b->graph_sig) {
+      if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+      }
+      hipGraph_t g;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return IHDG_ERR_HIP;
+      const hipError_t e = enqueue();
+      const hipError_t e2 = hipStreamEndCapture(st, &g);
+      if (e != hipSuccess || e2 != hipSuccess) return IHDG_ERR_HIP;
+      const hipError_t e3 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e3 != hipSuccess) {
+        b->graph = nullptr;
+        return IHDG_ERR_HIP;
+      }
+      b->graph_sig = sig;
+    }
+    if (hipGraphLaunch(b->graph, st) != hipSuccess) return IHDG_ERR_HIP;
+  } else if (enqueue() != hipSuccess) {
+    return IHDG_ERR_HIP;
   }
-  if (launch_reduce_batched(b->descs, (int)hd.size(), b->norms, st) != hipSuccess) return IHDG_ERR_HIP;
   std::vector<double> hn(2 * hd.size());
   if (hipMemcpyAsync(hn.data(), b->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)

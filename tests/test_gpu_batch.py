@@ -75,3 +75,45 @@ def test_batch_equals_single_solver_bitwise():
         b = solve_batch([(name, pr, prec)], 1e-11)
         assert b[name][0]["iters"] == res["iters"] + (0 if prec == 0 else 0)
         assert np.array_equal(b[name][1], u), name
+
+
+def _run_batch(items, tol, use_graphs, late=None, sweeps=16):
+    from paper_1605_03228_amd import Batch
+    from paper_1605_03228_amd.problem_io import make_solver
+    b = Batch(max_members=16, use_graphs=use_graphs)
+    tags = {}
+    for i, (name, pr, prec) in enumerate(items):
+        print(f"[gpu] batch(graphs={use_graphs}) add {name} prec={prec}", flush=True)
+        b.add(make_solver(pr, prec=prec, check_every=sweeps), tol, i)
+        tags[i] = name
+    out = {}
+    for rnd in range(100000):
+        if late is not None and rnd == 3:
+            name, pr, prec = late
+            b.add(make_solver(pr, prec=prec, check_every=sweeps), tol, len(tags))
+            tags[len(tags)] = name
+        n = b.round(sweeps)
+        for r in b.poll():
+            u = r["solver"].get_solution().reshape(r["solver"].sz["n_el"], -1).cpu().numpy()
+            out[tags[r["tag"]]] = (r["status"], r["iters"], u)
+            r["solver"].close()
+        if n == 0 and (late is None or rnd >= 3):
+            break
+    b.close()
+    return out
+
+
+def test_batch_graph_replay_equals_direct_launches():
+    """Rounds replayed from captured graphs (re-captured when members join,
+    leave or change mode) give bitwise the results of rounds launched
+    directly, with the batch's own eager work (defect / correction set-up
+    kernels, norm read-back) between the replays."""
+    items = mix()[:6]
+    late = ("late_t2_p3", w.config2(seed=5, n=10, p=3), 1)
+    g = _run_batch(items, 1e-10, True, late)
+    d = _run_batch(items, 1e-10, False, late)
+    assert set(g) == set(d) == {n for n, _, _ in items} | {late[0]}
+    for name in g:
+        assert g[name][0] == 0 and d[name][0] == 0, name
+        assert g[name][1] == d[name][1], name
+        assert np.array_equal(g[name][2], d[name][2]), name
