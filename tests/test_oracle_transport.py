@@ -236,10 +236,19 @@ def test_npc_terminates_after_J_sweeps_theorem2(make):
     assert rel(npc, u, ref) < 1e-12         # exact after J sweeps
 
 
-NPC_2D = [(16, 3, 9), (64, 3, 17), (256, 3, 33), (16, 4, 9), (64, 4, 17), (256, 4, 33)]
+GOLD_NPC = os.path.join(os.path.dirname(__file__), "golden", "table1_npc_iterations.txt")
 
 
-@pytest.mark.parametrize("n_el,p,iters", NPC_2D)
+def _gold_npc():
+    rows = []
+    for line in open(GOLD_NPC):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append(tuple(int(v) for v in line.split()))
+    return rows
+
+
+@pytest.mark.parametrize("n_el,p,iters", [r[1:] for r in _gold_npc() if r[0] == 2 and r[1] <= 256])
 def test_paper_table1_npc_2d_iteration_counts(n_el, p, iters):
     """Table 1, NPC column of the 2-D test: 2N+1 iterations on N x N elements (within one)."""
     n = int(round(np.sqrt(n_el)))
@@ -253,6 +262,24 @@ def test_paper_table1_npc_2d_iteration_counts(n_el, p, iters):
         if np.sqrt(np.einsum("ei,ij,ej->", d, M, d)) < 1e-10:
             break
     assert abs(k - iters) <= 1, (k, iters)
+
+
+@pytest.mark.parametrize("n_el,p,iters", [r[1:] for r in _gold_npc() if r[0] == 3 and r[1] <= 64])
+def test_paper_table1_npc_3d_iteration_counts(n_el, p, iters):
+    """Table 1, NPC column of the 3-D smooth test (stopping on the change of the
+    exact error): within two."""
+    n = int(round(n_el ** (1 / 3)))
+    pr = w.transport_e2(n, p)
+    o = TransportOperators(pr, flux="npc")
+    u = np.zeros((o.mesh.n_el, o.el.np))
+    prev = None
+    for k in range(1, 500):
+        u = o.sweep(u)
+        e = l2_error(o.mesh, o.el, u, lambda x: pr.exact(x)[..., 0])
+        if prev is not None and abs(e - prev) < 1e-10:
+            break
+        prev = e
+    assert abs(k - iters) <= 2, (k, iters)
 
 
 @pytest.mark.parametrize("n", [(1, 1), (1, 6), (7, 1), (1, 1, 1)])
