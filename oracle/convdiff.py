@@ -18,6 +18,14 @@ mu in Q^p(e), since tau^+ + tau^- = alpha.  Where alpha is constant on a face
 this is the paper's pointwise division by alpha; where it varies (affine beta)
 the weak form is kept so that the iHDG fixed point is the HDG solution.
 On the boundary uhat = g (Dirichlet), used at the quadrature points.
+
+Elliptic regime (the comment on iHDG for elliptic PDEs at the end of
+Section 4, beta = 0): the upwind choice gives tau = 1 and the iteration
+diverges on every mesh; the paper's mesh-dependent stabilisation
+tau* = gamma (p+1)(p+2)/h (gamma > d/4) makes it converge on meshes that are
+not too fine.  With prob.tau_gamma = gamma > 0, tau = tau* on both sides of
+every face (h: the smallest element edge), so alpha = tau^- + tau^+ = 2 tau*
+and the trace weights are tau* +- beta.n.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -58,6 +66,8 @@ class CDOperators:
         fq = prob.forcing(xq)[..., 0]
         F = np.zeros((ne, self.m * npn))
         F[:, d * npn:] = np.einsum("q,eq,qi->ei", W * J, fq, B)
+        self.tau_star = (prob.tau_gamma * (prob.p + 1) * (prob.p + 2) / float(np.min(self.mesh.h))
+                         if getattr(prob, "tau_gamma", 0.0) > 0 else None)
         self.bn = np.zeros((ne, nf, el.nfq))
         self.g = np.zeros((ne, nf, el.nfq))
         self.nbr = np.array([[mesh.neighbour(e, f) for f in range(nf)] for e in range(ne)])
@@ -69,7 +79,7 @@ class CDOperators:
             bn = np.einsum("eqa,a->eq", prob.beta_at(xf), nv)
             self.bn[:, f] = bn
             self.g[:, f] = prob.bdry(xf)[..., 0]
-            tau = 0.5 * (np.sqrt(bn * bn + 4.0) - bn)
+            tau = self.tau(bn)
             # <s.n + beta.n u + tau u, v>
             for a in range(d):
                 if nv[a] != 0:
@@ -79,7 +89,15 @@ class CDOperators:
         self.Ainv = np.linalg.inv(A)
 
     def tau(self, bn):
+        if self.tau_star is not None:
+            return np.full_like(bn, self.tau_star)
         return 0.5 * (np.sqrt(bn * bn + 4.0) - bn)
+
+    def alpha(self, bn):
+        """tau^- + tau^+ on a face with beta.n^- = bn."""
+        if self.tau_star is not None:
+            return np.full_like(bn, 2.0 * self.tau_star)
+        return np.sqrt(bn * bn + 4.0)
 
     def trace(self, U):
         """uhat^k at the face quadrature points of every element face: [ne, nf, nfq]."""
@@ -96,7 +114,7 @@ class CDOperators:
             inner = nb >= 0
             Un = U[np.where(inner, nb, 0)]
             bnm = self.bn[:, f]
-            alpha = np.sqrt(bnm * bnm + 4.0)
+            alpha = self.alpha(bnm)
             tm, tp = self.tau(bnm), self.tau(-bnm)
             snm = nv[a] * (U[:, a] @ Bf.T)
             snp = -nv[a] * (Un[:, a] @ Bo.T)
@@ -214,7 +232,7 @@ class CDOperators:
                     add(r0, fid[(e, f2)] * nfp, DA @ C[(e, f2)])
         for k, (em, fm, ep, fp) in enumerate(skel):
             _, Wf, _, Mu = el.face_q[fm]
-            alpha = np.sqrt(self.bn[em, fm] ** 2 + 4.0)
+            alpha = self.alpha(self.bn[em, fm])
             add(k * nfp, k * nfp, -np.einsum("q,q,qb,qc->cb", Wf * mesh.face_jac(fm), alpha, Mu, Mu))
         if nt == 0:  # no interior faces: the local solves with boundary data are the solution
             lam = np.zeros(0)
@@ -248,7 +266,8 @@ def brute_force_dense(prob, nq1=None):
     module docstring with uhat unknown.  Face rows, tested against Q^p(e): on
     an interior face the jump of the normal flux s.n + beta.n u + tau (u - uhat)
     vanishes (conservation); on a boundary face uhat = g.  A (p+4)-point Gauss
-    rule throughout, tau = (alpha - beta.n) / 2, alpha = sqrt((beta.n)^2 + 4).
+    rule throughout, tau = (alpha - beta.n) / 2, alpha = sqrt((beta.n)^2 + 4), or
+    tau = tau* on every face side when prob.tau_gamma > 0.
 
     Returns u_h(e, field, r_ref) -> value (field d = u).  Meant for meshes of
     2-4 elements.
@@ -265,6 +284,7 @@ def brute_force_dense(prob, nq1=None):
     fmodes = [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=dim - 1)]
     nv, nt = len(vmodes), len(fmodes)
     kinv, nu = 1.0 / prob.kappa, prob.nu
+    tstar = (prob.tau_gamma * (p + 1) * (p + 2) / float(np.min(mesh.h))) if getattr(prob, "tau_gamma", 0.0) > 0 else None
 
     def P(k, x):
         co = np.zeros(k + 1); co[k] = 1.0
@@ -338,7 +358,7 @@ def brute_force_dense(prob, nq1=None):
                 wq = (np.prod([wg[q] for q in qt]) if dim > 1 else 1.0) * Jf
                 x = x0 + mesh.h / 2 * (r + 1)
                 bn = prob.beta_at(x[None])[0] @ nvec
-                tau = 0.5 * (np.sqrt(bn * bn + 4.0) - bn)
+                tau = tstar if tstar is not None else 0.5 * (np.sqrt(bn * bn + 4.0) - bn)
                 rt = [r[cx] for cx in tang]
                 mus = [np.prod([P(fm[t], rt[t]) for t in range(dim - 1)]) if dim > 1 else 1.0 for fm in fmodes]
                 for i, mi in enumerate(vmodes):

@@ -50,6 +50,7 @@ class Problem:
     # convection-diffusion
     kappa: float = 1.0
     nu: float = 1.0
+    tau_gamma: float = 0.0                 # > 0: tau = tau_gamma (p+1)(p+2)/h on every face (elliptic regime)
     name: str = ""
     meta: dict = field(default_factory=dict)
 
@@ -321,6 +322,63 @@ def cd_smooth(n, p, kappa, nu=1.0):
     lap = lambda x, xp=np: -2.0 * PI * PI * u(x, xp)
     return _cd_problem(2, n, p, kappa, nu, beta, None, u, gu, lap,
                        name=f"cd_{n[0]}x{n[1]}_p{p}_k{kappa:g}")
+
+
+def cd_smooth3d(n, p, kappa, nu=1.0):
+    """The 3-D convection-diffusion experiments of Section 5.3 on the unit cube:
+    beta = (1 + z, 1 + x, 1 + y) (divergence free),
+    u^e = (1/pi) sin(pi x) cos(pi y) sin(pi z), Dirichlet data on every face."""
+    beta = lambda x, xp=np: xp.stack([1.0 + x[..., 2], 1.0 + x[..., 0], 1.0 + x[..., 1]], -1)
+    u = lambda x, xp=np: xp.sin(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * xp.sin(PI * x[..., 2]) / PI
+    gu = lambda x, xp=np: xp.stack([xp.cos(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * xp.sin(PI * x[..., 2]),
+                                   -xp.sin(PI * x[..., 0]) * xp.sin(PI * x[..., 1]) * xp.sin(PI * x[..., 2]),
+                                   xp.sin(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * xp.cos(PI * x[..., 2])], -1)
+    lap = lambda x, xp=np: -3.0 * PI * PI * u(x, xp)
+    return _cd_problem(3, n, p, kappa, nu, beta, None, u, gu, lap, name=f"cd3d_{n[0]}x{n[1]}x{n[2]}_p{p}_k{kappa:g}")
+
+
+def cd_elliptic(n, p, gamma=1.0, nu=0.0, exact="smooth", seed=0):
+    """The elliptic case of the end of Section 4: beta = 0, kappa = 1 (so
+    -lap u + nu u = f) on the unit square or cube, Dirichlet data from the exact
+    solution, stabilisation tau* = gamma (p+1)(p+2)/h (gamma = 0: the upwind
+    tau = 1, which the paper shows diverges).  exact = "smooth": the solution of
+    the 3-D convection-diffusion experiments of Section 5.3,
+    (1/pi) sin(pi x) cos(pi y) sin(pi z) (without the z factor in 2-D);
+    "poly": a random polynomial of degree 2 per direction."""
+    dim = len(n)
+    beta = lambda x, xp=np: xp.stack([x[..., 0] * 0] * dim, -1)
+    if exact == "smooth":
+        fz = (lambda x, xp: xp.sin(PI * x[..., 2])) if dim == 3 else (lambda x, xp: 1.0)
+        dz = (lambda x, xp: PI * xp.cos(PI * x[..., 2])) if dim == 3 else None
+        u = lambda x, xp=np: xp.sin(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * fz(x, xp) / PI
+
+        def gu(x, xp=np):
+            g = [xp.cos(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * fz(x, xp),
+                 -xp.sin(PI * x[..., 0]) * xp.sin(PI * x[..., 1]) * fz(x, xp)]
+            if dim == 3:
+                g.append(xp.sin(PI * x[..., 0]) * xp.cos(PI * x[..., 1]) * dz(x, xp) / PI)
+            return xp.stack(g, -1)
+        lap = lambda x, xp=np: -dim * PI * PI * u(x, xp)
+    else:
+        c = np.random.default_rng(seed).standard_normal(4 + 2 * (dim == 3))
+        z = (lambda x: x[..., 2]) if dim == 3 else (lambda x: x[..., 0] * 0)
+
+        def u(x, xp=np):
+            return (c[0] + c[1] * x[..., 0] + c[2] * x[..., 0] * x[..., 1] + c[3] * x[..., 1] ** 2
+                    + (c[4] * z(x) * x[..., 0] + c[5] * z(x) ** 2 if dim == 3 else 0.0))
+
+        def gu(x, xp=np):
+            g = [c[1] + c[2] * x[..., 1], c[2] * x[..., 0] + 2 * c[3] * x[..., 1]]
+            if dim == 3:
+                g[0] = g[0] + c[4] * z(x)
+                g.append(c[4] * x[..., 0] + 2 * c[5] * z(x))
+            return xp.stack(g, -1)
+        lap = lambda x, xp=np: x[..., 0] * 0 + 2 * c[3] + (2 * c[5] if dim == 3 else 0.0)
+    tag = "x".join(str(k) for k in n)
+    pr = _cd_problem(dim, n, p, 1.0, nu, beta, None, u, gu, lap, name=f"cd_elliptic_{tag}_p{p}_g{gamma:g}_nu{nu:g}",
+                     beta_const=(0.0,) * dim)
+    pr.tau_gamma = float(gamma)
+    return pr
 
 
 def config4b(eps=1e-4, n=128, p=4):
