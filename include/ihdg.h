@@ -138,6 +138,16 @@ typedef struct {
   double f0;         /* shallow water: Coriolis parameter (constant)                   */
   double gamma;      /* shallow water: bottom friction                                 */
   double mass_coef;  /* shallow water: coefficient a/dt of the mass term (a = 2: CN)   */
+  /* conv.-diff. stabilisation (the comment on elliptic PDEs closing Section 4).
+   * 0: the upwind flux, tau = (alpha - beta.n)/2 with alpha = sqrt((beta.n)^2 + 4).
+   * gamma > 0: the mesh-dependent tau* = gamma (p+1)(p+2)/h on every face, h the
+   * smallest element edge, so the trace is
+   *   uhat = (jump(s.n) + jump(beta.n u) + tau* (u- + u+)) / (2 tau*);
+   * the paper's analysis asks for gamma > d/4, and convergence of the iteration
+   * then holds only on meshes that are not too fine (solve with krylov_restart on
+   * fine meshes).  Negative values, or a nonzero value for another PDE, are
+   * IHDG_ERR_ARG.                                                                  */
+  double tau_gamma;
 } ihdg_coeffs;
 
 typedef struct {

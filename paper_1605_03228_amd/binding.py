@@ -37,7 +37,7 @@ class Coeffs(C.Structure):
                 ("sigma_el", C.c_void_p), ("f_q", C.c_void_p), ("g_fq", C.c_void_p),
                 ("beta_const", C.c_double * 3), ("sigma_const", C.c_double), ("kappa", C.c_double),
                 ("nu", C.c_double), ("Phi", C.c_double), ("f0", C.c_double), ("gamma", C.c_double),
-                ("mass_coef", C.c_double)]
+                ("mass_coef", C.c_double), ("tau_gamma", C.c_double)]
 
 
 class Options(C.Structure):
@@ -176,7 +176,7 @@ def _coeffs(c):
     bc = c.get("beta_const", (0.0, 0.0, 0.0))
     for a in range(3):
         cf.beta_const[a] = float(bc[a]) if a < len(bc) else 0.0
-    for k in ("sigma_const", "kappa", "nu", "Phi", "f0", "gamma", "mass_coef"):
+    for k in ("sigma_const", "kappa", "nu", "Phi", "f0", "gamma", "mass_coef", "tau_gamma"):
         setattr(cf, k, float(c.get(k, 0.0)))
     return cf
 

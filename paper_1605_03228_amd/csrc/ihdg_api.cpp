@@ -324,6 +324,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   if (o.inner_rtol <= 0) o.inner_rtol = 1e-6;
   if (o.krylov_restart < 0 || o.krylov_restart > kMaxRestart) return IHDG_ERR_UNSUPPORTED;
   if (pde == IHDG_CONVDIFF && !(coeffs->kappa > 0)) return IHDG_ERR_ARG;
+  if (!(coeffs->tau_gamma >= 0) || (pde != IHDG_CONVDIFF && coeffs->tau_gamma != 0)) return IHDG_ERR_ARG;
   if (pde == IHDG_SHALLOW_WATER && (!(coeffs->Phi > 0) || !(coeffs->mass_coef >= 0))) return IHDG_ERR_ARG;
   if (((uintptr_t)workspace & 255) || ((uintptr_t)scratch & 255)) return IHDG_ERR_ARG;
   const bool shared = decide_shared(pde, coeffs, &o);
@@ -427,6 +428,12 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   a.cf.f0 = coeffs->f0;
   a.cf.gamma = coeffs->gamma;
   a.cf.mass_coef = coeffs->mass_coef;
+  a.cf.tau_star = 0.0;
+  if (coeffs->tau_gamma > 0) {
+    double hmin = mi.h[0];
+    for (int k = 1; k < mi.dim; ++k) hmin = std::min(hmin, mi.h[k]);
+    a.cf.tau_star = coeffs->tau_gamma * (mi.p + 1) * (mi.p + 2) / hmin;
+  }
   a.pde = (int)pde;
   a.flux = (pde == IHDG_TRANSPORT && o.transport_flux == 1) ? 1 : 0;
   a.m = sz.m;

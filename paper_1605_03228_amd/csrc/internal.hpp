@@ -22,6 +22,7 @@ struct Coeffs {
   const double* g_fq;
   double beta_const[3];
   double sigma_const, kappa, nu, Phi, f0, gamma, mass_coef;
+  double tau_star;  // conv.-diff.: 0 = upwind tau; > 0 = the fixed tau* on every face
 };
 
 struct SetupArgs {

@@ -103,7 +103,11 @@ struct ElemData {
   double sigma;
 };
 
-__device__ inline double tau_cd(double bn) { return 0.5 * (sqrt(bn * bn + 4.0) - bn); }
+// Conv.-diff. stabilisation on a face with outward beta.n = bn: the upwind
+// (alpha - bn)/2, or the fixed mesh-dependent tau* when one is set.
+__device__ inline double tau_cd(double bn, double tau_star) {
+  return tau_star > 0 ? tau_star : 0.5 * (sqrt(bn * bn + 4.0) - bn);
+}
 
 __device__ void load_element(const SetupArgs& a, int64_t e, bool all_interior, ElemData& d) {
   const MeshInfo& m = a.mi;
@@ -222,7 +226,7 @@ __device__ double entry_L(const SetupArgs& a, const Basis& b, const ElemData& d,
     if (!b.on_face(f, ni) || !b.on_face(f, nj)) continue;
     for (int qf = 0; qf < a.mi.nfq; ++qf) {
       double bn = d.bn[f][qf];
-      v += b.Wf(f, qf) * (bn + tau_cd(bn)) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+      v += b.Wf(f, qf) * (bn + tau_cd(bn, c.tau_star)) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
     }
   }
   return v;
@@ -253,7 +257,7 @@ __device__ double entry_E(const SetupArgs& a, const Basis& b, const ElemData& d,
     return (fi - 1 == ax) ? -c.Phi * face_sign(f) * fm : 0.0;
   }
   if (fi < dim) return (fi == ax) ? -face_sign(f) * face_mass(b, f, ni, nj, nullptr) : 0.0;
-  for (int qf = 0; qf < a.mi.nfq; ++qf) w[qf] = tau_cd(d.bn[f][qf]);
+  for (int qf = 0; qf < a.mi.nfq; ++qf) w[qf] = tau_cd(d.bn[f][qf], c.tau_star);
   return face_mass(b, f, ni, nj, w);
 }
 
@@ -277,7 +281,7 @@ __device__ double entry_F(const SetupArgs& a, const Basis& b, const ElemData& d,
       } else if (fi < dim) {
         if (fi == ax) v -= face_sign(f) * wq;  // -<g, t . n>
       } else {
-        v += wq * tau_cd(bn);              // <tau g, v>
+        v += wq * tau_cd(bn, a.cf.tau_star);  // <tau g, v>
       }
     }
   }
@@ -340,12 +344,20 @@ __device__ void cd_projection(const SetupArgs& a, const Basis& b, const ElemData
       int ib = fnode(a.mi.n1, dim, f, bb);
       double m0 = 0, ma = 0, mp = 0, mm = 0;
       for (int qf = 0; qf < a.mi.nfq; ++qf) {
-        double bn = d.bn[f][qf], al = sqrt(bn * bn + 4.0);
+        double bn = d.bn[f][qf];
         double w = b.Wf(f, qf) * b.Bf(f, qf, ib) * b.Bf(f, qf, ic);
         m0 += w;
-        ma += w * al;
-        mm += w * 0.5 * (al + bn);
-        mp += w * 0.5 * (al - bn);
+        if (a.cf.tau_star > 0) {  // tau- = tau+ = tau*: weights tau* +- bn over 2 tau*
+          const double ts = a.cf.tau_star;
+          ma += w * 2.0 * ts;
+          mm += w * (ts + bn);
+          mp += w * (ts - bn);
+        } else {                  // upwind: alpha and (alpha +- bn)/2
+          const double al = sqrt(bn * bn + 4.0);
+          ma += w * al;
+          mm += w * 0.5 * (al + bn);
+          mp += w * 0.5 * (al - bn);
+        }
       }
       Ma[cc * nfp + bb] = ma;
       R[cc * 3 * nfp + bb] = m0;

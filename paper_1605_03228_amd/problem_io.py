@@ -3,7 +3,8 @@ quadrature points and return the device arrays ihdg_setup reads.
 
 `problem` is any object with the attributes of a problem description
 (pde, dim, n, p, lo, hi, beta / beta_const, div_beta, sigma_el /
-sigma_const, forcing, bdry, Phi, f0, gamma, dt, a_mass, kappa, nu); its
+sigma_const, forcing, bdry, Phi, f0, gamma, dt, a_mass, kappa, nu,
+tau_gamma); its
 callables take (x[..., dim], xp) and are evaluated here with xp = torch on
 the device.  This is input marshalling only: no part of the method runs here.
 """
@@ -61,6 +62,7 @@ def coefficients(problem, device="cuda", shared=None):
         c["f_q"] = f.contiguous()
     elif pde == "cd":
         c["kappa"], c["nu"] = problem.kappa, problem.nu
+        c["tau_gamma"] = getattr(problem, "tau_gamma", 0.0)
         c["f_q"] = problem.forcing(xq, None, torch).contiguous()
     else:
         c["Phi"], c["f0"], c["gamma"] = problem.Phi, problem.f0, problem.gamma

@@ -54,8 +54,10 @@ def footprint_bytes(problem, **opts):
 
 def needs_krylov(problem):
     """Convection-diffusion at kappa >= 1e-2 (with nu = 1): outside the region where
-    the plain iteration converges on these meshes (the paper's Tables 3-4)."""
-    return problem.pde == "cd" and problem.kappa >= 1e-2
+    the plain iteration converges on these meshes (the paper's Tables 3-4).  Also
+    every request with the elliptic stabilisation tau*: its iteration converges
+    only on coarse meshes, and slowly there (the end of Section 4)."""
+    return problem.pde == "cd" and (problem.kappa >= 1e-2 or getattr(problem, "tau_gamma", 0.0) > 0)
 
 
 class Server:

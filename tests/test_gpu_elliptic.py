@@ -1,0 +1,124 @@
+"""The elliptic regime on the GPU path against the oracle: beta = 0, kappa = 1,
+the mesh-dependent stabilisation tau* = gamma (p+1)(p+2)/h (the comment on
+iHDG for elliptic PDEs that closes Section 4).
+
+* per-sweep iterates agree with the oracle's to 1e-12 (relative, h-norm) and
+  converged solutions with its direct solve to 1e-10 (FP64) / 1e-8 (mixed),
+  shared-operator and per-element paths;
+* the upwind tau = 1 diverges on the GPU as in the oracle;
+* where the tau* iteration diverges (gamma = 0.6) or is slow on a fine mesh,
+  GMRES on the iHDG operator reaches the direct solution;
+* a negative gamma, or a nonzero one for another PDE, is rejected at setup.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as w
+from oracle.convdiff import CDOperators
+from oracle.norms import h_norm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1605_03228_amd import binding
+    binding.load()
+
+
+def _solver(pr, **kw):
+    from paper_1605_03228_amd.problem_io import make_solver
+    print(f"[gpu] {pr.name} n={pr.n} p={pr.p} {kw}", flush=True)
+    return make_solver(pr, **kw)
+
+
+def _u(s):
+    u = s.get_solution()
+    torch.cuda.synchronize()
+    return u.reshape(u.shape[0], -1).cpu().numpy()
+
+
+def _rel(o, a, b):
+    return h_norm(o.mesh, o.el, a - b) / h_norm(o.mesh, o.el, b)
+
+
+CASES = [
+    ("shared_6x5_p3", lambda: w.cd_elliptic((6, 5), 3, gamma=1.0, nu=1.0), {}),
+    ("per_element_6x5_p3", lambda: w.cd_elliptic((6, 5), 3, gamma=1.0, nu=1.0), {"shared": False}),
+    ("shared_9x9_p2_nu10", lambda: w.cd_elliptic((9, 9), 2, gamma=1.0, nu=10.0), {}),
+    ("single_element_p4", lambda: w.cd_elliptic((1, 1), 4, gamma=1.0, nu=1.0), {}),
+    ("gamma2_4x7_p1", lambda: w.cd_elliptic((4, 7), 1, gamma=2.0, nu=1.0), {}),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+def test_tau_star_per_sweep_and_converged(name, make, kw):
+    pr = make()
+    o = CDOperators(pr)
+    s = _solver(pr, **kw)
+    u = np.zeros((o.mesh.n_el, s.sz["n_loc"]))
+    for k in (1, 3):
+        s.sweep(k)
+        for _ in range(k):
+            u = o.sweep(u)
+        r = _rel(o, _u(s), u)
+        assert r < 1e-12, (k, r)
+    s.close()
+    ud = o.direct_hdg()
+    for prec, bar in ((0, 1e-10), (1, 1e-8)):
+        s = _solver(pr, prec=prec, **kw)
+        res = s.solve(1e-13 if prec == 0 else 1e-12)
+        assert res["status"] == 0, res
+        r = _rel(o, _u(s), ud)
+        print(f"  prec={prec}: {res['iters']} iterations, rel err {r:.2e}", flush=True)
+        assert r < bar
+        s.close()
+
+
+def test_upwind_tau_one_diverges():
+    pr = w.cd_elliptic((4, 4), 2, gamma=0.0, nu=1.0)
+    s = _solver(pr, max_iters=5000)
+    res = s.solve(1e-12)
+    assert res["status"] == 6, res  # diverged
+    s.close()
+
+
+@pytest.mark.parametrize("gamma,n,p", [(0.6, 8, 3), (1.0, 24, 2)], ids=["divergent", "fine_mesh"])
+def test_gmres_on_the_ihdg_operator(gamma, n, p):
+    """gamma = 0.6 on 8 x 8, p = 3: the iteration diverges; gamma = 1 on 24 x 24,
+    p = 2: it converges, slowly.  GMRES (restart 60) reaches the direct solve."""
+    pr = w.cd_elliptic((n, n), p, gamma=gamma, nu=1.0)
+    o = CDOperators(pr)
+    s = _solver(pr, krylov_restart=60, max_iters=20000)
+    res = s.solve(1e-12)
+    assert res["status"] == 0, res
+    r = _rel(o, _u(s), o.direct_hdg())
+    print(f"  gmres: {res['krylov_iters']} Krylov iterations, rel err {r:.2e}", flush=True)
+    assert r < 1e-9
+    s.close()
+    if gamma == 1.0:
+        s = _solver(pr, max_iters=100000)
+        res2 = s.solve(1e-12)
+        print(f"  plain iHDG: status {res2['status']}, {res2['iters']} sweeps", flush=True)
+        assert res2["status"] == 0
+        assert res2["iters"] > 10 * res["krylov_iters"]
+        s.close()
+
+
+def test_invalid_tau_gamma_rejected():
+    from paper_1605_03228_amd import binding
+    pr = w.cd_elliptic((3, 3), 2, gamma=-1.0, nu=1.0)
+    with pytest.raises(binding.IhdgError) as e:
+        _solver(pr)
+    assert e.value.status == 1
+    pr = w.transport_const((3, 3), 2, (1.0, 0.5))
+    from paper_1605_03228_amd.problem_io import coefficients
+    c = coefficients(pr, "cuda", None)
+    c["tau_gamma"] = 1.0
+    print(f"[gpu] transport with tau_gamma = 1 (rejected)", flush=True)
+    with pytest.raises(binding.IhdgError) as e:
+        binding.Solver(pr.n, pr.p, binding.TRANSPORT, c, device="cuda")
+    assert e.value.status == 1
