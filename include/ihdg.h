@@ -154,9 +154,14 @@ typedef struct {
   ihdg_precision prec;
   int32_t check_every;     /* sweeps per convergence check (0 = library default, 16)           */
   int32_t max_iters;       /* sweep cap of ihdg_solve (0 = 100000)                            */
-  int32_t krylov_restart;  /* 0: plain iHDG; 0 < m <= 256: GMRES(m) on (I - T)u = c, T the sweep */
+  int32_t krylov_restart;  /* 0: plain iHDG; 0 < m <= 256: GMRES(m) on (I - T)u = c, T the sweep.
+                              With prec = IHDG_MIXED every restart forms the true residual with
+                              one FP64 sweep, and the cycle runs with the FP32 operators and an
+                              FP32 basis ((m+1) x 4 bytes per unknown instead of 8), updating u
+                              in FP64; the tolerance is the same FP64 relative residual       */
   double inner_rtol;       /* mixed: inner FP32 loop stops when its increment <= this x the
-                              correction (0 = 1e-6)                                           */
+                              correction; mixed GMRES: a cycle ends once its residual estimate
+                              fell by this factor (0 = 1e-6)                                  */
   int32_t use_graph;       /* 1: replay sweep batches from a captured HIP graph               */
   int32_t force_per_element; /* 1: per-element operators even where one could be shared      */
   int32_t block_waves;     /* launch shape of the sweep kernel: 0 = autotuned at setup (cached per
@@ -169,6 +174,15 @@ typedef struct {
                               1 = the NPC flux analysed after Theorem 1 (eq. Ntaub): tau = 0 on outflow,
                               |beta.n| on inflow, so the iteration terminates after as many sweeps as the
                               mesh has flow layers (Theorem 2); same fixed point                        */
+  int32_t krylov_method;   /* 0: GMRES(krylov_restart) as above.  1: BiCGStab (van der Vorst) on
+                              (I - T)u = c, FP64, two sweeps per iteration and six vectors of
+                              workspace, scalars kept on the device; krylov_restart must be > 0
+                              to select a Krylov solve and is otherwise unused; the recursive
+                              residual is confirmed by the true one before IHDG_OK, and the
+                              iteration restarts from the current u when they disagree.  max_iters
+                              caps the iterations; prec must be IHDG_FP64 (else IHDG_ERR_UNSUPPORTED).
+                              The iHDG sweep as the Krylov operator is the use the paper suggests
+                              for regimes where the plain iteration fails (end of Section 4)      */
 } ihdg_options;
 
 /* Discretisation sizes for (mesh, order, pde).  No device work. */
@@ -321,6 +335,9 @@ ihdg_status ihdg_batch_poll(ihdg_batch* b, ihdg_batch_result* out, int32_t max_o
  * the same; 1 by default on a non-null stream.  enable = 0: launch directly.
  * The results are the same either way. */
 ihdg_status ihdg_batch_use_graphs(ihdg_batch* b, int32_t enable);
+/* The HIP call that last failed in a batch call (its name and the runtime's
+ * error name), for IHDG_ERR_HIP; "" if none.  Owned by the batch. */
+const char* ihdg_batch_last_error(const ihdg_batch* b);
 void ihdg_batch_destroy(ihdg_batch* b);
 
 const char* ihdg_last_error(const ihdg_ctx* ctx);

@@ -44,7 +44,7 @@ class Options(C.Structure):
     _fields_ = [("prec", C.c_int), ("check_every", C.c_int32), ("max_iters", C.c_int32),
                 ("krylov_restart", C.c_int32), ("inner_rtol", C.c_double), ("use_graph", C.c_int32),
                 ("force_per_element", C.c_int32), ("block_waves", C.c_int32), ("time_stepping", C.c_int32),
-                ("transport_flux", C.c_int32)]
+                ("transport_flux", C.c_int32), ("krylov_method", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -67,7 +67,8 @@ EXPORTS = ["ihdg_sizes", "ihdg_quadrature_points", "ihdg_footprint", "ihdg_setup
            "ihdg_solve", "ihdg_residual", "ihdg_get_solution", "ihdg_set_solution", "ihdg_set_stream",
            "ihdg_get_stats", "ihdg_last_error", "ihdg_status_string", "ihdg_destroy",
            "ihdg_batch_footprint", "ihdg_batch_create", "ihdg_batch_add", "ihdg_batch_round",
-           "ihdg_batch_poll", "ihdg_batch_use_graphs", "ihdg_batch_destroy", "ihdg_time_step", "ihdg_node_points"]
+           "ihdg_batch_poll", "ihdg_batch_use_graphs", "ihdg_batch_destroy", "ihdg_batch_last_error",
+           "ihdg_time_step", "ihdg_node_points"]
 
 
 def load():
@@ -109,8 +110,11 @@ def load():
     lib.ihdg_node_points.argtypes = [P(Mesh), C.c_int32, C.c_void_p, C.c_void_p]
     lib.ihdg_batch_destroy.argtypes = [C.c_void_p]
     lib.ihdg_batch_destroy.restype = None
+    lib.ihdg_batch_last_error.argtypes = [C.c_void_p]
+    lib.ihdg_batch_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("ihdg_last_error", "ihdg_status_string", "ihdg_destroy", "ihdg_batch_destroy"):
+        if name not in ("ihdg_last_error", "ihdg_status_string", "ihdg_destroy", "ihdg_batch_destroy",
+                        "ihdg_batch_last_error"):
             getattr(lib, name).restype = C.c_int
     _LIB = lib
     return lib
@@ -126,9 +130,11 @@ def _mesh(n, lo=None, hi=None):
     return m
 
 
-def _check(st, ctx=None):
+def _check(st, ctx=None, batch=None):
     if st != OK:
         msg = load().ihdg_last_error(ctx).decode() if ctx else ""
+        if batch:
+            msg = load().ihdg_batch_last_error(batch).decode()
         raise IhdgError(st, msg)
 
 
@@ -182,12 +188,15 @@ def _coeffs(c):
 
 
 def _options(prec=FP64, check_every=16, max_iters=0, krylov_restart=0, inner_rtol=0.0, use_graph=True,
-             force_per_element=False, block_waves=0, flux="upwind", time_stepping=False):
+             force_per_element=False, block_waves=0, flux="upwind", time_stepping=False, krylov="gmres"):
+    """krylov = "gmres" (GMRES(krylov_restart) when krylov_restart > 0) or
+    "bicgstab" (selects the Krylov solve by itself)."""
     o = Options()
     o.prec = prec
     o.check_every = check_every
     o.max_iters = max_iters
-    o.krylov_restart = krylov_restart
+    o.krylov_method = {"gmres": 0, "bicgstab": 1}[krylov]
+    o.krylov_restart = max(krylov_restart, 1) if krylov == "bicgstab" else krylov_restart
     o.inner_rtol = inner_rtol
     o.use_graph = 1 if use_graph else 0
     o.force_per_element = 1 if force_per_element else 0
@@ -314,7 +323,7 @@ class Batch:
 
     def round(self, sweeps=16):
         n = C.c_int32()
-        _check(self.lib.ihdg_batch_round(self.h, sweeps, C.byref(n)))
+        _check(self.lib.ihdg_batch_round(self.h, sweeps, C.byref(n)), batch=self.h)
         return n.value
 
     def poll(self):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -42,7 +43,7 @@ struct ihdg_ctx {
   double* norms;     // device scratch for reductions (64 doubles)
   double* Ht;        // time stepping: H = mass_coef L^{-1} M_Phi (shared), or null
   double* cf;        // time stepping: the forcing part of c, A^{-1} F
-  double* kry;       // Krylov basis, (m+1) vectors (or null)
+  void* kry;         // Krylov basis, (m+1) vectors, FP64 (FP32 on the mixed path), or null
   double* kry_part;  // Krylov scratch: dot partials, Hessenberg columns, coefficients
   int cur;
   int cur32;
@@ -178,7 +179,7 @@ struct Layout {
 static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared, bool mixed, int krylov,
-                          bool timestep = false) {
+                          bool timestep = false, int kmethod = 0) {
   Layout L{};
   const size_t nvec = (size_t)m.n_blk * kLanes * sz.n_loc;
   const size_t nG = shared ? (size_t)sz.n_loc * sz.n_in : nvec * sz.n_in;
@@ -212,8 +213,12 @@ static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared
     L.off_Ht = take((size_t)sz.n_loc * sz.n_loc * 8);
     L.off_cf = take(nvec * 8);
   }
-  if (krylov > 0) {
-    L.off_kry = take(nvec * 8 * (size_t)(krylov + 1));
+  if (krylov > 0 && kmethod == 1) {
+    // BiCGStab: [rhat | r], [s | t], p, v; dot partials (kDotGroups x 2) and 16 scalars
+    L.off_kry = take(nvec * 8 * 6);
+    L.off_krypart = take(((size_t)ihdg::kDotGroups * 2 + 16) * 8);
+  } else if (krylov > 0) {
+    L.off_kry = take(nvec * (mixed ? 4 : 8) * (size_t)(krylov + 1));
     // dot partials (kDotGroups x (m+1)), Hessenberg columns ((m+1) x m), the
     // current Gram-Schmidt coefficients (m+1), 8 scalars, solution coefficients (m)
     const size_t m1 = (size_t)krylov + 1;
@@ -300,7 +305,7 @@ ihdg_status ihdg_footprint(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, c
   bool mixed = opts && opts->prec == IHDG_MIXED;
   int kry = opts ? opts->krylov_restart : 0;
   if (kry < 0 || kry > kMaxRestart) return IHDG_ERR_UNSUPPORTED;
-  Layout L = make_layout(mi, sz, shared, mixed, kry, opts && opts->time_stepping);
+  Layout L = make_layout(mi, sz, shared, mixed, kry, opts && opts->time_stepping, opts ? opts->krylov_method : 0);
   *persistent_bytes = L.total;
   *scratch_bytes = L.scratch;
   return IHDG_OK;
@@ -323,6 +328,8 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   if (o.max_iters <= 0) o.max_iters = 100000;
   if (o.inner_rtol <= 0) o.inner_rtol = 1e-6;
   if (o.krylov_restart < 0 || o.krylov_restart > kMaxRestart) return IHDG_ERR_UNSUPPORTED;
+  if (o.krylov_method != 0 && o.krylov_method != 1) return IHDG_ERR_ARG;
+  if (o.krylov_method == 1 && o.krylov_restart > 0 && o.prec != IHDG_FP64) return IHDG_ERR_UNSUPPORTED;
   if (pde == IHDG_CONVDIFF && !(coeffs->kappa > 0)) return IHDG_ERR_ARG;
   if (!(coeffs->tau_gamma >= 0) || (pde != IHDG_CONVDIFF && coeffs->tau_gamma != 0)) return IHDG_ERR_ARG;
   if (pde == IHDG_SHALLOW_WATER && (!(coeffs->Phi > 0) || !(coeffs->mass_coef >= 0))) return IHDG_ERR_ARG;
@@ -340,7 +347,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
       break;
     default: return IHDG_ERR_ARG;
   }
-  Layout L = make_layout(mi, sz, shared, mixed, o.krylov_restart, o.time_stepping != 0);
+  Layout L = make_layout(mi, sz, shared, mixed, o.krylov_restart, o.time_stepping != 0, o.krylov_method);
   if (workspace_bytes < L.total) return IHDG_ERR_NOMEM;
   const size_t ncol = shared ? (size_t)(2 * sz.n_loc + sz.n_in) : (size_t)(sz.n_loc + sz.n_in + 1);
   const size_t per = (size_t)sz.n_loc * ncol * 8;
@@ -378,7 +385,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   int* flags = (int*)(ws + L.off_flags);
   c->Ht = (o.time_stepping && shared) ? (double*)(ws + L.off_Ht) : nullptr;
   c->cf = (o.time_stepping && shared) ? (double*)(ws + L.off_cf) : nullptr;
-  c->kry = o.krylov_restart > 0 ? (double*)(ws + L.off_kry) : nullptr;
+  c->kry = o.krylov_restart > 0 ? (void*)(ws + L.off_kry) : nullptr;
   c->kry_part = o.krylov_restart > 0 ? (double*)(ws + L.off_krypart) : nullptr;
   c->cur = 0;
   c->cur32 = 0;
@@ -583,7 +590,15 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
   }
   std::vector<int> cand = c->shared ? std::vector<int>{4, 8, 3} : std::vector<int>{1, 2, 4, 8};
   if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::direct_supported(c->mi.dim, c->mi.p)) cand.push_back(5);
-  hipEvent_t e0, e1;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  struct Events {  // destroyed on every return path
+    hipEvent_t* a;
+    hipEvent_t* b;
+    ~Events() {
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } guard{&e0, &e1};
   hipError_t e = hipEventCreate(&e0);
   if (e != hipSuccess) return e;
   e = hipEventCreate(&e1);
@@ -622,8 +637,6 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
       bw = w;
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   *best = bw;
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tuned[key] = bw;
@@ -666,11 +679,18 @@ static hipError_t run_batch(ihdg_ctx* c, bool fp32, int n) {
   hipGraphExec_t* slot = fp32 ? &c->g32[parity] : &c->g64[parity];
   const int p0 = parity;
   if (!*slot) {
-    hipGraph_t g;
+    // direct launches if the capture is invalidated by other threads'
+    // synchronising calls (see ihdg_batch_round)
+    hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     e = fp32 ? batch32_enqueue(c, n) : batch64_enqueue(c, n);
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    if (e == hipErrorStreamCaptureInvalidated || e2 == hipErrorStreamCaptureInvalidated) {
+      (void)hipGetLastError();
+      parity = p0;  // nothing of the capture ran
+      return fp32 ? batch32_enqueue(c, n) : batch64_enqueue(c, n);
+    }
     if (e != hipSuccess) return e;
     if (e2 != hipSuccess) return e2;
     e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
@@ -788,6 +808,7 @@ static ihdg_status solve_mixed(ihdg_ctx* c, double tol, int32_t* iters, double* 
 }
 
 static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr);
+static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr);
 
 extern "C" {
 
@@ -810,7 +831,8 @@ ihdg_status ihdg_solve(ihdg_ctx* c, double tol, int32_t* iters, double* final_in
   c->stats.fp64_sweeps = c->stats.fp32_sweeps = 0;
   c->stats.outer_steps = c->stats.krylov_iters = 0;
   ihdg_status s;
-  if (c->opt.krylov_restart > 0) s = solve_gmres(c, tol, iters, final_incr);
+  if (c->opt.krylov_restart > 0 && c->opt.krylov_method == 1) s = solve_bicgstab(c, tol, iters, final_incr);
+  else if (c->opt.krylov_restart > 0) s = solve_gmres(c, tol, iters, final_incr);
   else if (c->mixed) s = solve_mixed(c, tol, iters, final_incr);
   else s = solve_fp64(c, tol, iters, final_incr);
   if (final_defect && (s == IHDG_OK || s == IHDG_ERR_MAXITER)) {
@@ -874,14 +896,24 @@ ihdg_status ihdg_set_solution(ihdg_ctx* c, const double* u_dev) {
 // steps enqueued past convergence are discarded (their basis vectors are not
 // used in the update).
 // ---------------------------------------------------------------------------
-static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
+// GMRES(m) on (I - T)u = c, the sweep T as the operator.  VT = double: the
+// basis, the operator and the update in FP64.  VT = float (the mixed path):
+// every restart forms the true residual r = psi(u) - u in FP64 (one FP64
+// sweep), one cycle of GMRES(m) on (I - T)d = r runs with the FP32 operators
+// and an FP32 basis (dot products and the Hessenberg matrix in FP64), and u
+// += d in FP64 -- iterative refinement with a Krylov inner solver.  A cycle
+// also ends once its own residual estimate has fallen by inner_rtol, the
+// level FP32 can resolve.
+template <typename VT>
+static ihdg_status solve_gmres_t(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
+  constexpr bool f32 = std::is_same<VT, float>::value;
   constexpr int kCheck = 8;
   const int m = c->opt.krylov_restart;
   const int m1 = m + 1;
   const int64_t N = c->nvec;
   const int n_loc = c->sz.n_loc;
   hipStream_t st = c->stream;
-  double* V = c->kry;  // (m+1) vectors
+  VT* V = (VT*)c->kry;  // (m+1) vectors
   auto vec = [&](int j) { return V + (size_t)j * N; };
   double* part = c->kry_part;                              // kDotGroups x (m+1)
   double* Hc = part + (size_t)ihdg::kDotGroups * m1;       // column j at Hc + j (m+1)
@@ -893,23 +925,31 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
   double rel = INFINITY;
   double* u = c->u64[c->cur];
   double* tmp = c->tmp64;
-  auto norm2 = [&](const double* x, double* out) -> hipError_t {
+  auto norm2 = [&](const auto* x, double* out) -> hipError_t {
     hipError_t e = launch_kdots(x, x, N, 1, c->wnorm, n_loc, part, scal, nullptr, 0, st);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(st);
   };
-  // A v = v - psi(v) + c  written into out
-  auto apply = [&](const double* v, double* out) -> hipError_t {
-    hipError_t e = one_sweep(c, false, v, out, c->c64);
-    if (e != hipSuccess) return e;
-    c->stats.fp64_sweeps += 1;
-    return launch_kapply(out, v, c->c64, N, st);
+  // A v = v - psi(v) + c (FP64), or v - T v with the FP32 operators and a zero
+  // affine part (d32 holds zeros during the solve), written into out
+  auto apply = [&](const VT* v, VT* out) -> hipError_t {
+    if constexpr (f32) {
+      hipError_t e = one_sweep(c, true, v, out, c->d32);
+      if (e != hipSuccess) return e;
+      c->stats.fp32_sweeps += 1;
+      return launch_kapply_linear(out, v, N, st);
+    } else {
+      hipError_t e = one_sweep(c, false, v, out, c->c64);
+      if (e != hipSuccess) return e;
+      c->stats.fp64_sweeps += 1;
+      return launch_kapply(out, v, c->c64, N, st);
+    }
   };
   // one Arnoldi step: V_{j+1} from V_j, Hessenberg column j on the device
   auto arnoldi = [&](int j) -> hipError_t {
-    double* w = vec(j + 1);
+    VT* w = vec(j + 1);
     double* hcol = Hc + (size_t)j * m1;
     hipError_t e = apply(vec(j), w);
     for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
@@ -927,14 +967,27 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
     bnorm = std::sqrt(std::max(d, 0.0));
   }
   if (bnorm == 0.0) bnorm = 1.0;
+  if constexpr (f32) HIPCHK(c, launch_fill_zero_f32(c->d32, N, st));
+  const double eta = f32 ? std::max(c->opt.inner_rtol, 1e-7) : 0.0;
   while (it < c->opt.max_iters) {
-    // r = c - A u  -> V0
-    HIPCHK(c, apply(u, tmp));
-    HIPCHK(c, hipMemcpyAsync(vec(0), c->c64, N * 8, hipMemcpyDeviceToDevice, st));
-    HIPCHK(c, launch_axpby(vec(0), 1.0, tmp, -1.0, N, st));
-    double rr;
-    HIPCHK(c, norm2(vec(0), &rr));
-    double beta = std::sqrt(std::max(rr, 0.0));
+    double beta;
+    if constexpr (f32) {
+      // r = psi(u) - u in FP64 -> V0 = r / |r| in FP32
+      HIPCHK(c, one_sweep(c, false, u, tmp, c->c64));
+      c->stats.fp64_sweeps += 1;
+      HIPCHK(c, launch_axpby(tmp, 1.0, u, -1.0, N, st));
+      double rr;
+      HIPCHK(c, norm2(tmp, &rr));
+      beta = std::sqrt(std::max(rr, 0.0));
+    } else {
+      // r = c - A u  -> V0
+      HIPCHK(c, apply(u, tmp));
+      HIPCHK(c, hipMemcpyAsync(vec(0), c->c64, N * 8, hipMemcpyDeviceToDevice, st));
+      HIPCHK(c, launch_axpby(vec(0), 1.0, tmp, -1.0, N, st));
+      double rr;
+      HIPCHK(c, norm2(vec(0), &rr));
+      beta = std::sqrt(std::max(rr, 0.0));
+    }
     rel = beta / bnorm;
     if (final_incr) *final_incr = rel;
     if (!std::isfinite(beta)) return fail(c, IHDG_ERR_DIVERGED, "non-finite residual");
@@ -942,7 +995,11 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
       if (iters) *iters = (int32_t)it;
       return IHDG_OK;
     }
-    HIPCHK(c, launch_axpby(vec(0), 1.0 / beta, vec(0), 0.0, N, st));
+    if constexpr (f32) {
+      HIPCHK(c, launch_scale_to_f32(vec(0), tmp, 1.0 / beta, N, st));
+    } else {
+      HIPCHK(c, launch_axpby(vec(0), 1.0 / beta, vec(0), 0.0, N, st));
+    }
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int used = 0;  // basis vectors entering the update
@@ -973,7 +1030,7 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
         used = j + 1;
         rel = std::fabs(g[j + 1]) / bnorm;
         if (!std::isfinite(rel)) return fail(c, IHDG_ERR_DIVERGED, "non-finite Krylov residual");
-        if (rel <= tol) {
+        if (rel <= tol || std::fabs(g[j + 1]) <= eta * beta) {
           conv = true;
           break;
         }
@@ -995,6 +1052,97 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
     if (iters) *iters = (int32_t)it;
   }
   return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
+}
+
+static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
+  return c->mixed ? solve_gmres_t<float>(c, tol, iters, final_incr) : solve_gmres_t<double>(c, tol, iters, final_incr);
+}
+
+// BiCGStab (van der Vorst) on (I - T)u = c, the sweep T as the operator, in
+// FP64.  Each iteration: rho = (rhat, r) with |r|^2 in the same pass, p, v =
+// A p, (rhat, v), s, t = A s, (t, s) and (t, t) in one pass, then x and r in
+// one pass; the scalars stay in device memory (the update kernels read them),
+// so the host waits only at the convergence checks every kCheck iterations.
+// When the recursive residual meets the tolerance, the true residual is
+// formed with one sweep; if it does not, the iteration restarts from u.
+static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
+  constexpr int kCheck = 8;
+  const int64_t N = c->nvec;
+  const int n_loc = c->sz.n_loc;
+  hipStream_t st = c->stream;
+  double* B = (double*)c->kry;
+  double* rh = B;          // [rhat | r] adjacent: one pass gives (rhat, r) and (r, r)
+  double* r = B + N;
+  double* sv = B + 2 * N;  // [s | t] adjacent: one pass gives (t, s) and (t, t)
+  double* t = B + 3 * N;
+  double* p = B + 4 * N;
+  double* v = B + 5 * N;
+  double* part = c->kry_part;                          // kDotGroups x 2
+  double* sc = part + (size_t)ihdg::kDotGroups * 2;    // 16 scalars
+  double* u = c->u64[c->cur];
+  double hsc[16];
+  // v_out = (I - T) v_in
+  auto apply = [&](const double* vin, double* vout) -> hipError_t {
+    hipError_t e = one_sweep(c, false, vin, vout, c->c64);
+    if (e != hipSuccess) return e;
+    c->stats.fp64_sweeps += 1;
+    return launch_kapply(vout, vin, c->c64, N, st);
+  };
+  auto readsc = [&]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, st);
+    return e == hipSuccess ? hipStreamSynchronize(st) : e;
+  };
+  double bnorm;
+  HIPCHK(c, launch_kdots(c->c64, c->c64, N, 1, c->wnorm, n_loc, part, sc + 7, nullptr, 0, st));
+  HIPCHK(c, readsc());
+  bnorm = std::sqrt(std::max(hsc[7], 0.0));
+  if (bnorm == 0.0) bnorm = 1.0;
+  int64_t it = 0;
+  for (int restart = 0; restart < 1000; ++restart) {
+    // true residual r = psi(u) - u = c - (I - T) u; rhat = r
+    HIPCHK(c, one_sweep(c, false, u, r, c->c64));
+    c->stats.fp64_sweeps += 1;
+    HIPCHK(c, launch_axpby(r, 1.0, u, -1.0, N, st));
+    HIPCHK(c, hipMemcpyAsync(rh, r, N * 8, hipMemcpyDeviceToDevice, st));
+    HIPCHK(c, launch_kdots(r, r, N, 1, c->wnorm, n_loc, part, sc + 7, nullptr, 0, st));
+    HIPCHK(c, readsc());
+    const double rn = std::sqrt(std::max(hsc[7], 0.0));
+    if (final_incr) *final_incr = rn / bnorm;
+    if (iters) *iters = (int32_t)it;
+    if (!std::isfinite(rn)) return fail(c, IHDG_ERR_DIVERGED, "non-finite residual");
+    if (rn <= tol * bnorm) return IHDG_OK;
+    if (it >= c->opt.max_iters) return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
+    // rho_1 = (rhat, r) and |r|^2 into the parity-1 slot
+    int q = 1;
+    HIPCHK(c, launch_kdots(r, rh, N, 2, c->wnorm, n_loc, part, sc + 8 + 2 * q, nullptr, 0, st));
+    bool first = true, again = false;
+    while (it < c->opt.max_iters && !again) {
+      const int n = (int)std::min<int64_t>(kCheck, c->opt.max_iters - it);
+      for (int k = 0; k < n; ++k) {
+        HIPCHK(c, launch_bicg_p(p, r, v, sc, q, first ? 1 : 0, N, st));
+        first = false;
+        HIPCHK(c, apply(p, v));
+        HIPCHK(c, launch_kdots(v, rh, N, 1, c->wnorm, n_loc, part, sc + 2, nullptr, 0, st));
+        HIPCHK(c, launch_bicg_s(sv, r, v, sc, q, N, st));
+        HIPCHK(c, apply(sv, t));
+        HIPCHK(c, launch_kdots(t, sv, N, 2, c->wnorm, n_loc, part, sc + 5, nullptr, 0, st));
+        HIPCHK(c, launch_bicg_xr(u, r, p, sv, t, sc, N, st));
+        q ^= 1;
+        HIPCHK(c, launch_kdots(r, rh, N, 2, c->wnorm, n_loc, part, sc + 8 + 2 * q, nullptr, 0, st));
+        ++it;
+        c->stats.krylov_iters += 1;
+      }
+      HIPCHK(c, readsc());
+      const double rr = hsc[9 + 2 * q];  // |r|^2 after the last update
+      const double rel = std::sqrt(std::max(rr, 0.0)) / bnorm;
+      if (final_incr) *final_incr = rel;
+      if (iters) *iters = (int32_t)it;
+      if (!std::isfinite(rr) || !std::isfinite(hsc[3]) || !std::isfinite(hsc[4]))
+        return fail(c, IHDG_ERR_DIVERGED, "BiCGStab breakdown (non-finite scalar)");
+      if (rel <= tol || hsc[8 + 2 * q] == 0.0) again = true;  // converged, or rho = 0: confirm / restart
+    }
+  }
+  return fail(c, IHDG_ERR_MAXITER, "too many BiCGStab restarts");
 }
 
 // ---------------------------------------------------------------------------
@@ -1085,6 +1233,8 @@ ihdg_status ihdg_batch_create(int32_t max_members, int64_t max_blocks, void* wor
   *out = b;
   return IHDG_OK;
 }
+
+const char* ihdg_batch_last_error(const ihdg_batch* b) { return b ? b->err.c_str() : ""; }
 
 void ihdg_batch_destroy(ihdg_batch* b) {
   if (!b) return;
@@ -1192,9 +1342,17 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
     gl.push_back(g);
   }
   if ((int64_t)ho.size() > b->max_blocks) return IHDG_ERR_NOMEM;
-  if (hipMemcpyAsync(b->descs, hd.data(), hd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(b->owner, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess)
+  // a failing HIP call: its name and the runtime's error name go to b->err
+  auto bfail = [&](const char* what, hipError_t e) {
+    b->err = std::string(what) + ": " + hipGetErrorName(e);
     return IHDG_ERR_HIP;
+  };
+  if (hipError_t e = hipMemcpyAsync(b->descs, hd.data(), hd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, st);
+      e != hipSuccess)
+    return bfail("copy descriptors", e);
+  if (hipError_t e = hipMemcpyAsync(b->owner, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice, st);
+      e != hipSuccess)
+    return bfail("copy block owners", e);
   auto enqueue = [&]() -> hipError_t {
     for (int s = 0; s < S; ++s) {
       for (const G& g : gl) {
@@ -1223,27 +1381,42 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
       }
-      hipGraph_t g;
-      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return IHDG_ERR_HIP;
+      // Synchronising calls that other threads of the caller make meanwhile
+      // (e.g. Krylov solves on streams of their own) can invalidate the
+      // capture on this runtime even in thread-local mode; the round then runs
+      // with direct launches (the graph of an invalidated capture is left to
+      // the runtime) and the next round captures again.
+      hipGraph_t g = nullptr;
+      if (hipError_t e0 = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal); e0 != hipSuccess)
+        return bfail("begin capture", e0);
       const hipError_t e = enqueue();
       const hipError_t e2 = hipStreamEndCapture(st, &g);
-      if (e != hipSuccess || e2 != hipSuccess) return IHDG_ERR_HIP;
-      const hipError_t e3 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(g);
-      if (e3 != hipSuccess) {
-        b->graph = nullptr;
-        return IHDG_ERR_HIP;
+      if (e == hipErrorStreamCaptureInvalidated || e2 == hipErrorStreamCaptureInvalidated) {
+        (void)hipGetLastError();  // the failed launch's error, not a device fault
+        if (hipError_t e4 = enqueue(); e4 != hipSuccess) return bfail("launch after an invalidated capture", e4);
+      } else {
+        if (e != hipSuccess) return bfail("launch during capture", e);
+        if (e2 != hipSuccess) return bfail("end capture", e2);
+        const hipError_t e3 = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e3 != hipSuccess) {
+          b->graph = nullptr;
+          return bfail("instantiate graph", e3);
+        }
+        b->graph_sig = sig;
       }
-      b->graph_sig = sig;
     }
-    if (hipGraphLaunch(b->graph, st) != hipSuccess) return IHDG_ERR_HIP;
-  } else if (enqueue() != hipSuccess) {
-    return IHDG_ERR_HIP;
+    if (b->graph && b->graph_sig == sig) {
+      if (hipError_t e = hipGraphLaunch(b->graph, st); e != hipSuccess) return bfail("launch graph", e);
+    }
+  } else if (hipError_t e = enqueue(); e != hipSuccess) {
+    return bfail("launch", e);
   }
   std::vector<double> hn(2 * hd.size());
-  if (hipMemcpyAsync(hn.data(), b->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return IHDG_ERR_HIP;
+  if (hipError_t e = hipMemcpyAsync(hn.data(), b->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+      e != hipSuccess)
+    return bfail("copy norms", e);
+  if (hipError_t e = hipStreamSynchronize(st); e != hipSuccess) return bfail("synchronize", e);
   // state machines
   std::vector<char> finished(b->active.size(), 0);
   for (size_t slot = 0; slot < order.size(); ++slot) {

@@ -129,7 +129,10 @@ hipError_t launch_fill_zero_f64(double* x, int64_t n, hipStream_t s);
 hipError_t launch_to_user(const double* u_il, double* u_user, int64_t n_el, int n_loc, hipStream_t s);
 hipError_t launch_from_user(const double* u_user, double* u_il, int64_t n_el, int n_loc, hipStream_t s);
 hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t n, hipStream_t s);
+// w -= sum_j h[j] V_j (FP64 sums; FP64 or FP32 storage; an FP32 basis may update an FP64 w)
 hipError_t launch_multi_axpy(double* w, const double* V, const double* h, int k, int64_t n, hipStream_t s);
+hipError_t launch_multi_axpy(float* w, const float* V, const double* h, int k, int64_t n, hipStream_t s);
+hipError_t launch_multi_axpy(double* w, const float* V, const double* h, int k, int64_t n, hipStream_t s);
 // norms[2 i + j] = sum over member i's blocks of its partials (fixed order)
 hipError_t launch_reduce_batched(const BatchDesc* descs, int n, double* norms, hipStream_t s);
 // Krylov helpers.  launch_kdots: out[j] = <x, V + j nvec>_h for j < k
@@ -139,7 +142,20 @@ constexpr int kDotGroups = 1024;
 int kdot_groups(int64_t nvec);
 hipError_t launch_kdots(const double* x, const double* V, int64_t nvec, int k, const double* w, int n_loc,
                         double* partial, double* out, double* acc, int accumulate, hipStream_t s);
+hipError_t launch_kdots(const float* x, const float* V, int64_t nvec, int k, const double* w, int n_loc,
+                        double* partial, double* out, double* acc, int accumulate, hipStream_t s);
 hipError_t launch_knormalize(double* v, int64_t n, const double* nn, double* hn, hipStream_t s);
+hipError_t launch_knormalize(float* v, int64_t n, const double* nn, double* hn, hipStream_t s);
 hipError_t launch_kapply(double* out, const double* v, const double* c, int64_t n, hipStream_t s);
+// out <- v - out (the FP32 Krylov operator from a sweep with zero affine part)
+hipError_t launch_kapply_linear(float* out, const float* v, int64_t n, hipStream_t s);
+// out <- (float)(scale * x)
+hipError_t launch_scale_to_f32(float* out, const double* x, double scale, int64_t n, hipStream_t s);
+// BiCGStab updates with their scalars in device memory (layout in vector_ops.hip)
+hipError_t launch_bicg_p(double* p, const double* r, const double* v, const double* sc, int q, int first, int64_t n,
+                         hipStream_t s);
+hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* sc, int q, int64_t n, hipStream_t s);
+hipError_t launch_bicg_xr(double* x, double* r, const double* p, const double* sv, const double* t, double* sc,
+                          int64_t n, hipStream_t s);
 
 }  // namespace ihdg

@@ -73,17 +73,26 @@ __global__ void k_from_user(const double* __restrict__ us, double* __restrict__ 
   }
 }
 
-// Weighted inner products <x, y_j>_h for j < k over the interleaved layout:
-// one partial per (block, j), then a fixed-order sum per j.
 // Weighted inner products <x, V_j>_h for the basis vectors V_j = V + j * nvec,
-// j < k.  Grid (G, ceil(k / 8)): workgroup (g, c) takes products 8c .. 8c + 7
-// over the entries g * 256 + t, strided by G * 256 (G fixed by the vector
-// length, so the summation order is too), accumulating 8 sums per thread.
-// partial[g * k + j]: workgroup g's share, summed in a fixed order (entries of
-// a thread, lanes by the butterfly, then the 4 waves).
-__global__ __launch_bounds__(256) void k_kdots_partial(const double* __restrict__ x, const double* __restrict__ V,
+// j < k.  Grid (G, ceil(k / 8)): workgroup (g, c) takes products 8c .. 8c + 7.
+// Each thread loads 16 bytes per vector at a time (VW = 2 FP64 or 4 FP32
+// entries, which share one row of the [blk][row][lane] layout and so one norm
+// weight), at chunk g * 256 + t, strided by G * 256 chunks (G fixed by the
+// vector length, so the summation order is too), accumulating 8 sums per
+// thread in FP64.  partial[g * k + j]: workgroup g's share, summed in a fixed
+// order (entries of a thread, lanes by the butterfly, then the 4 waves).
+// Basis and vector in FP64, or both in FP32 (the mixed-precision Krylov basis).
+template <typename T>
+struct alignas(16) Vec16 {
+  static constexpr int n = 16 / sizeof(T);
+  T v[n];
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_kdots_partial(const T* __restrict__ x, const T* __restrict__ V,
                                                        int64_t nvec, int k, const double* __restrict__ w, int n_loc,
                                                        double* __restrict__ partial) {
+  constexpr int VW = Vec16<T>::n;
   __shared__ double red[4][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int j0 = blockIdx.y * 8;
@@ -91,13 +100,24 @@ __global__ __launch_bounds__(256) void k_kdots_partial(const double* __restrict_
   double s[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) s[j] = 0.0;
+  const int64_t nch = nvec / VW;  // nvec is a multiple of 64
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < nvec; o += stride) {
-    const int r = (int)((o >> 6) % n_loc);  // [blk][row][lane] layout
-    const double xw = w[r] * x[o];
+  for (int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x; ch < nch; ch += stride) {
+    const int64_t o = ch * VW;
+    const int r = (int)((uint32_t)(o >> 6) % (uint32_t)n_loc);  // [blk][row][lane] layout
+    const Vec16<T> xv = *(const Vec16<T>*)(x + o);
+    double xw[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) xw[e] = w[r] * (double)xv.v[e];
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      if (j < kk) s[j] += xw * V[(int64_t)(j0 + j) * nvec + o];
+      if (j < kk) {
+        const Vec16<T> vv = *(const Vec16<T>*)(V + (int64_t)(j0 + j) * nvec + o);
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) t += xw[e] * (double)vv.v[e];
+        s[j] += t;
+      }
   }
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -136,29 +156,100 @@ __global__ __launch_bounds__(256) void k_kdots_final(const double* __restrict__ 
 
 // v <- v / sqrt(nn) (nn on the device; v untouched if nn <= 0), and the norm
 // stored at *hn
-__global__ void k_knormalize(double* __restrict__ v, int64_t n, const double* __restrict__ nn, double* __restrict__ hn) {
+template <typename T>
+__global__ void k_knormalize(T* __restrict__ v, int64_t n, const double* __restrict__ nn, double* __restrict__ hn) {
   const double h = sqrt(fmax(*nn, 0.0));
   if (blockIdx.x == 0 && threadIdx.x == 0) *hn = h;
   if (!(h > 0.0)) return;
   const double inv = 1.0 / h;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    v[i] = inv * v[i];
+    v[i] = (T)(inv * (double)v[i]);
 }
 
-// out <- (v - out) + c: the Krylov operator (I - T) v from the sweep psi(v) in out
+// out <- (v - out) + c: the Krylov operator (I - T) v from the sweep psi(v) in
+// out (FP64); out <- v - out: the same from a sweep with zero affine part (FP32)
 __global__ void k_kapply(double* __restrict__ out, const double* __restrict__ v, const double* __restrict__ c,
                          int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     out[i] = (v[i] - out[i]) + c[i];
 }
+__global__ void k_kapply_linear(float* __restrict__ out, const float* __restrict__ v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = v[i] - out[i];
+}
 
-// w -= sum_j h[j] V_j, V_j = V + j * n (contiguous basis vectors), h on the device
-__global__ void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, const double* __restrict__ h, int k,
+// w -= sum_j h[j] V_j, V_j = V + j * n (contiguous basis vectors), h on the
+// device; the sum in FP64 whatever the storage of w and V.  Each thread takes
+// VW consecutive entries (VW = 4 when both are FP32, else 2) with one wide load
+// per vector; n is a multiple of 64.
+template <typename TW, typename TV>
+__global__ void k_multi_axpy(TW* __restrict__ w, const TV* __restrict__ V, const double* __restrict__ h, int k,
                              int64_t n) {
+  constexpr int VW = (sizeof(TW) == 4 && sizeof(TV) == 4) ? 4 : 2;
+  struct alignas(sizeof(TW) * VW) WV { TW v[VW]; };
+  struct alignas(sizeof(TV) * VW) VV { TV v[VW]; };
+  const int64_t nch = n / VW;
+  for (int64_t ch = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ch < nch; ch += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = ch * VW;
+    WV wv = *(const WV*)(w + i);
+    double s[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) s[e] = (double)wv.v[e];
+    for (int j = 0; j < k; ++j) {
+      const double hj = h[j];
+      const VV vv = *(const VV*)(V + (int64_t)j * n + i);
+#pragma unroll
+      for (int e = 0; e < VW; ++e) s[e] -= hj * (double)vv.v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < VW; ++e) wv.v[e] = (TW)s[e];
+    *(WV*)(w + i) = wv;
+  }
+}
+
+// out <- (float)(scale * x)
+__global__ void k_scale_to_f32(float* __restrict__ out, const double* __restrict__ x, double scale, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (float)(scale * x[i]);
+}
+
+// BiCGStab vector updates (van der Vorst's BiCGStab, each scalar read from
+// device memory so the iteration needs no host round trip).  sc layout:
+// [2] (rhat, v), [3] alpha, [4] omega, [5] (t, s), [6] (t, t),
+// [8 + 2q] rho of iterations of parity q, [9 + 2q] the squared residual norm
+// computed with it.
+// An exact zero in a denominator (the iteration has hit the solution, e.g. a
+// mesh without interior faces, where I - T = I) gives a zero scalar, so u stays
+// finite and the next convergence check sees r = 0.
+// p <- r (first) or r + beta (p - omega v), beta = (rho_q / rho_{1-q}) (alpha / omega)
+__global__ void k_bicg_p(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
+                         const double* __restrict__ sc, int q, int first, int64_t n) {
+  const double rp = sc[8 + 2 * (1 - q)], om0 = sc[4];
+  const double beta = (first || rp == 0.0 || om0 == 0.0) ? 0.0 : (sc[8 + 2 * q] / rp) * (sc[3] / om0);
+  const double om = sc[4];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = first ? r[i] : r[i] + beta * (p[i] - om * v[i]);
+}
+// alpha = rho_q / (rhat, v) (stored by one thread; the others compute it too);
+// s <- r - alpha v
+__global__ void k_bicg_s(double* __restrict__ s, const double* __restrict__ r, const double* __restrict__ v,
+                         double* __restrict__ sc, int q, int64_t n) {
+  const double alpha = sc[2] != 0.0 ? sc[8 + 2 * q] / sc[2] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[3] = alpha;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s[i] = r[i] - alpha * v[i];
+}
+// omega = (t, s) / (t, t) (stored by one thread); x <- x + alpha p + omega s;
+// r <- s - omega t
+__global__ void k_bicg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
+                          const double* __restrict__ s, const double* __restrict__ t, double* __restrict__ sc,
+                          int64_t n) {
+  const double alpha = sc[3];
+  const double omega = sc[6] != 0.0 ? sc[5] / sc[6] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[4] = omega;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double s = w[i];
-    for (int j = 0; j < k; ++j) s -= h[j] * V[(int64_t)j * n + i];
-    w[i] = s;
+    x[i] += alpha * p[i] + omega * s[i];
+    r[i] = s[i] - omega * t[i];
   }
 }
 
@@ -248,7 +339,15 @@ hipError_t launch_axpby(double* y, double a, const double* x, double b, int64_t 
   return hipGetLastError();
 }
 hipError_t launch_multi_axpy(double* w, const double* V, const double* h, int k, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_multi_axpy, dim3(grid_for(n)), dim3(256), 0, s, w, V, h, k, n);
+  hipLaunchKernelGGL((k_multi_axpy<double, double>), dim3(grid_for(n / 2)), dim3(256), 0, s, w, V, h, k, n);
+  return hipGetLastError();
+}
+hipError_t launch_multi_axpy(float* w, const float* V, const double* h, int k, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_multi_axpy<float, float>), dim3(grid_for(n / 4)), dim3(256), 0, s, w, V, h, k, n);
+  return hipGetLastError();
+}
+hipError_t launch_multi_axpy(double* w, const float* V, const double* h, int k, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_multi_axpy<double, float>), dim3(grid_for(n / 2)), dim3(256), 0, s, w, V, h, k, n);
   return hipGetLastError();
 }
 hipError_t launch_time_rhs(double* c, const double* cf, const double* H, const double* u, const double* psi,
@@ -268,17 +367,52 @@ int kdot_groups(int64_t nvec) {
   return (int)(g < 1 ? 1 : (g > kDotGroups ? kDotGroups : g));
 }
 
-hipError_t launch_kdots(const double* x, const double* V, int64_t nvec, int k, const double* w, int n_loc,
-                        double* partial, double* out, double* acc, int accumulate, hipStream_t s) {
+template <typename T>
+static hipError_t kdots(const T* x, const T* V, int64_t nvec, int k, const double* w, int n_loc, double* partial,
+                        double* out, double* acc, int accumulate, hipStream_t s) {
   if (k <= 0 || nvec <= 0) return hipErrorInvalidValue;
   const int g = kdot_groups(nvec);
-  hipLaunchKernelGGL(k_kdots_partial, dim3((unsigned)g, (unsigned)((k + 7) / 8)), dim3(256), 0, s, x, V, nvec, k, w,
-                     n_loc, partial);
+  hipLaunchKernelGGL(k_kdots_partial<T>, dim3((unsigned)g, (unsigned)((k + 7) / 8)), dim3(256), 0, s, x, V, nvec, k,
+                     w, n_loc, partial);
   hipLaunchKernelGGL(k_kdots_final, dim3((unsigned)k), dim3(256), 0, s, partial, g, k, out, acc, accumulate);
   return hipGetLastError();
 }
+hipError_t launch_kdots(const double* x, const double* V, int64_t nvec, int k, const double* w, int n_loc,
+                        double* partial, double* out, double* acc, int accumulate, hipStream_t s) {
+  return kdots(x, V, nvec, k, w, n_loc, partial, out, acc, accumulate, s);
+}
+hipError_t launch_kdots(const float* x, const float* V, int64_t nvec, int k, const double* w, int n_loc,
+                        double* partial, double* out, double* acc, int accumulate, hipStream_t s) {
+  return kdots(x, V, nvec, k, w, n_loc, partial, out, acc, accumulate, s);
+}
 hipError_t launch_knormalize(double* v, int64_t n, const double* nn, double* hn, hipStream_t s) {
-  hipLaunchKernelGGL(k_knormalize, dim3(grid_for(n)), dim3(256), 0, s, v, n, nn, hn);
+  hipLaunchKernelGGL(k_knormalize<double>, dim3(grid_for(n)), dim3(256), 0, s, v, n, nn, hn);
+  return hipGetLastError();
+}
+hipError_t launch_knormalize(float* v, int64_t n, const double* nn, double* hn, hipStream_t s) {
+  hipLaunchKernelGGL(k_knormalize<float>, dim3(grid_for(n)), dim3(256), 0, s, v, n, nn, hn);
+  return hipGetLastError();
+}
+hipError_t launch_bicg_p(double* p, const double* r, const double* v, const double* sc, int q, int first, int64_t n,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_p, dim3(grid_for(n)), dim3(256), 0, s, p, r, v, sc, q, first, n);
+  return hipGetLastError();
+}
+hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* sc, int q, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_s, dim3(grid_for(n)), dim3(256), 0, s, sv, r, v, sc, q, n);
+  return hipGetLastError();
+}
+hipError_t launch_bicg_xr(double* x, double* r, const double* p, const double* sv, const double* t, double* sc,
+                          int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_bicg_xr, dim3(grid_for(n)), dim3(256), 0, s, x, r, p, sv, t, sc, n);
+  return hipGetLastError();
+}
+hipError_t launch_kapply_linear(float* out, const float* v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_kapply_linear, dim3(grid_for(n)), dim3(256), 0, s, out, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_scale_to_f32(float* out, const double* x, double scale, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_to_f32, dim3(grid_for(n)), dim3(256), 0, s, out, x, scale, n);
   return hipGetLastError();
 }
 hipError_t launch_kapply(double* out, const double* v, const double* c, int64_t n, hipStream_t s) {

@@ -17,9 +17,11 @@ being solved.  The loop
 
 Requests the plain iteration cannot solve (convection-diffusion with a
 diffusion coefficient in the region where the paper's Tables 3-4 show the
-iteration diverging) are routed at admission to GMRES with the sweep as its
-operator, run on a worker thread with a stream of its own so they overlap with
-the batch.  If a batched request diverges anyway it is re-queued for GMRES.
+iteration diverging, and the elliptic stabilisation) are routed at admission to
+a Krylov solve with the sweep as its operator (GMRES by default, BiCGStab on
+request), run on a worker thread with a stream of its own so they overlap with
+the batch.  If a batched request diverges anyway it is re-queued for the
+Krylov path.
 
 All numerical work runs in libihdg.so; this module only schedules.
 """
@@ -63,7 +65,7 @@ def needs_krylov(problem):
 class Server:
     def __init__(self, hbm_budget_bytes=64 << 30, sweeps=16, max_members=256, max_blocks=1 << 22,
                  device="cuda", krylov_workers=3, krylov_restart=40, keep_solutions=False, progress=0,
-                 setup_workers=2):
+                 setup_workers=2, krylov="gmres"):
         self.budget = hbm_budget_bytes
         self.sweeps = sweeps
         self.max_members = max_members
@@ -71,6 +73,7 @@ class Server:
         self.device = device
         self.krylov_workers = krylov_workers
         self.krylov_restart = krylov_restart
+        self.krylov = krylov  # "gmres" (GMRES(krylov_restart)) or "bicgstab"
         self.keep = keep_solutions
         self.progress = progress
         self.setup_workers = setup_workers
@@ -81,7 +84,8 @@ class Server:
             torch.cuda.set_device(dev.index)
         side = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(side):
-            s = make_solver(problem, device=self.device, krylov_restart=self.krylov_restart, max_iters=200000)
+            s = make_solver(problem, device=self.device, krylov=self.krylov, krylov_restart=self.krylov_restart,
+                            max_iters=200000)
             res = s.solve(tol)
             u = s.get_solution().cpu() if self.keep else None
             s.close()
@@ -177,7 +181,7 @@ class Server:
                 for r in batch.poll():
                     rid = r["tag"]
                     s = r["solver"]
-                    if r["status"] == 6:  # diverged: hand over to GMRES
+                    if r["status"] == 6:  # diverged: hand over to the Krylov path
                         s.close()
                         used -= mem.pop(rid)
                         rec[rid]["requeue"] = True

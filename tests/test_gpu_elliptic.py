@@ -108,6 +108,41 @@ def test_gmres_on_the_ihdg_operator(gamma, n, p):
         s.close()
 
 
+@pytest.mark.parametrize("gamma,n,p", [(0.6, 8, 3), (1.0, 24, 2)], ids=["divergent", "fine_mesh"])
+def test_mixed_gmres_on_the_ihdg_operator(gamma, n, p):
+    """GMRES on the mixed path (FP32 operators and basis within a cycle, FP64
+    residual at every restart) reaches the same solution, to the mixed bar
+    (1e-8): the FP64 residual tolerance is the same, but the error it leaves is
+    amplified by the operator's conditioning, which grows fast with refinement
+    in this regime."""
+    pr = w.cd_elliptic((n, n), p, gamma=gamma, nu=1.0)
+    o = CDOperators(pr)
+    s = _solver(pr, krylov_restart=60, max_iters=20000, prec=1)
+    res = s.solve(1e-12)
+    assert res["status"] == 0, res
+    r = _rel(o, _u(s), o.direct_hdg())
+    print(f"  mixed gmres: {res['krylov_iters']} Krylov iterations, {res['fp64_sweeps']} FP64 sweeps, "
+          f"rel err {r:.2e}", flush=True)
+    assert r < 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("gamma,n,p", [(0.6, 8, 3), (1.0, 24, 2), (1.0, 1, 3)],
+                         ids=["divergent", "fine_mesh", "single_element"])
+def test_bicgstab_on_the_ihdg_operator(gamma, n, p):
+    """BiCGStab (two sweeps per iteration, no basis) reaches the direct solve;
+    on a single element I - T = I and the iteration hits the solution at once."""
+    pr = w.cd_elliptic((n, n), p, gamma=gamma, nu=1.0)
+    o = CDOperators(pr)
+    s = _solver(pr, krylov="bicgstab", max_iters=20000)
+    res = s.solve(1e-12)
+    assert res["status"] == 0, res
+    r = _rel(o, _u(s), o.direct_hdg())
+    print(f"  bicgstab: {res['krylov_iters']} iterations, {res['fp64_sweeps']} sweeps, rel err {r:.2e}", flush=True)
+    assert r < 1e-9
+    s.close()
+
+
 def test_invalid_tau_gamma_rejected():
     from paper_1605_03228_amd import binding
     pr = w.cd_elliptic((3, 3), 2, gamma=-1.0, nu=1.0)

@@ -108,3 +108,28 @@ def test_fullsize_cd_eps1e2_gmres():
     el2 = l2_rel(o, u, ref)
     print(f"cfg4b eps=1e-2 gmres: {res['krylov_iters']} iterations, rel err {err:.3e} (h-norm), {el2:.3e} (L2)")
     assert err < 1e-9 and el2 < 1e-9
+
+
+def test_fullsize_cd_eps1e2_bicgstab():
+    """The same solve with BiCGStab on the iHDG operator."""
+    pr, o, ref = reference("cfg4b_1e-2", lambda: w.config4b(eps=1e-2))
+    res, u = run(pr, 1e-12, krylov="bicgstab", max_iters=20000)
+    assert res["status"] == 0, res
+    err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
+    el2 = l2_rel(o, u, ref)
+    print(f"cfg4b eps=1e-2 bicgstab: {res['krylov_iters']} iterations ({res['fp64_sweeps']} sweeps), "
+          f"rel err {err:.3e} (h-norm), {el2:.3e} (L2)")
+    assert err < 1e-9 and el2 < 1e-9
+
+
+def test_fullsize_cd_eps1e2_mixed_gmres():
+    """The same solve on the mixed path: FP32 operators and Krylov basis within
+    each GMRES(100) cycle, the true FP64 residual at every restart."""
+    pr, o, ref = reference("cfg4b_1e-2", lambda: w.config4b(eps=1e-2))
+    res, u = run(pr, 1e-12, krylov_restart=100, max_iters=20000, prec=1)
+    assert res["status"] == 0, res
+    err = h_norm(o.mesh, o.el, u - ref) / h_norm(o.mesh, o.el, ref)
+    el2 = l2_rel(o, u, ref)
+    print(f"cfg4b eps=1e-2 mixed gmres: {res['krylov_iters']} iterations ({res['fp64_sweeps']} FP64 sweeps), "
+          f"rel err {err:.3e} (h-norm), {el2:.3e} (L2)")
+    assert err < 1e-9 and el2 < 1e-9

@@ -123,6 +123,68 @@ def test_gmres_where_ihdg_diverges():
     assert rel(o, gpu_u(s2), o.direct_hdg()) < 1e-9
 
 
+def test_bicgstab_where_ihdg_diverges():
+    """BiCGStab with the sweep as operator: same solution as the oracle's direct
+    solve; deterministic run to run (fixed-grid dot products)."""
+    pr = w.cd_smooth((6, 6), 4, kappa=1e-2)
+    o = oracle_for(pr)
+    ref = o.direct_hdg()
+    us = []
+    for _ in range(2):
+        s = gpu_solver(pr, krylov="bicgstab")
+        res = s.solve(1e-12)
+        assert res["status"] == 0, res
+        us.append(gpu_u(s))
+        print(f"  bicgstab: {res['krylov_iters']} iterations, {res['fp64_sweeps']} sweeps, "
+              f"rel err {rel(o, us[-1], ref):.2e}", flush=True)
+    assert rel(o, us[0], ref) < 1e-9
+    assert np.array_equal(us[0], us[1])
+
+
+def test_bicgstab_rejects_mixed_and_unknown_method():
+    from paper_1605_03228_amd import binding
+    pr = w.cd_smooth((3, 3), 2, kappa=1e-2)
+    with pytest.raises(binding.IhdgError) as e:
+        gpu_solver(pr, krylov="bicgstab", prec=1)
+    assert e.value.status == 2
+    # an unknown method, through the C ABI directly
+    import ctypes as C
+    from paper_1605_03228_amd.problem_io import coefficients
+    lib = binding.load()
+    cf = binding._coeffs(coefficients(pr, "cuda", None))
+    o = binding._options(krylov_restart=10)
+    o.krylov_method = 7
+    mesh = binding._mesh(pr.n, None, None)
+    pb, sb = C.c_size_t(), C.c_size_t()
+    assert lib.ihdg_footprint(C.byref(mesh), pr.p, binding.CD, C.byref(cf), C.byref(o), C.byref(pb), C.byref(sb)) == 0
+    ws = torch.empty(pb.value, dtype=torch.uint8, device="cuda")
+    scr = torch.empty(sb.value, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    ctx = C.c_void_p()
+    print("[gpu] krylov_method = 7 (rejected)", flush=True)
+    st = lib.ihdg_setup(C.byref(mesh), pr.p, binding.CD, C.byref(cf), C.byref(o), C.c_void_p(ws.data_ptr()),
+                        pb.value, C.c_void_p(scr.data_ptr()), sb.value, None, C.byref(ctx))
+    assert st == 1
+
+
+def test_mixed_gmres_where_ihdg_diverges():
+    """The same with prec = mixed: FP32 operators and basis inside each cycle,
+    the FP64 residual at every restart; same tolerance, same bar."""
+    pr = w.cd_smooth((6, 6), 4, kappa=1e-2)
+    o = oracle_for(pr)
+    ref = o.direct_hdg()
+    s = gpu_solver(pr, krylov_restart=15, prec=1)
+    res = s.solve(1e-12)
+    assert res["status"] == 0, res
+    assert res["fp32_sweeps"] > 0 and res["fp64_sweeps"] > 0
+    assert rel(o, gpu_u(s), ref) < 1e-9
+    s64 = gpu_solver(pr, krylov_restart=15)
+    r64 = s64.solve(1e-12)
+    print(f"  mixed: {res['krylov_iters']} Krylov iterations ({res['fp64_sweeps']} FP64 sweeps), "
+          f"FP64: {r64['krylov_iters']}", flush=True)
+    assert res["krylov_iters"] <= 1.5 * r64["krylov_iters"] + 10
+
+
 def test_mixed_sign_interior_face_rejected():
     """beta = (0.5 - y, 1) on 3x3 quads: beta.n changes sign inside the x-faces that
     straddle y = 0.5 -> unsupported (such a face needs both traces)."""
