@@ -179,7 +179,9 @@ typedef struct {
                               workspace, scalars kept on the device; krylov_restart must be > 0
                               to select a Krylov solve and is otherwise unused; the recursive
                               residual is confirmed by the true one before IHDG_OK, and the
-                              iteration restarts from the current u when they disagree.  max_iters
+                              iteration restarts from the current u when they disagree or when
+                              the recursive residual has not improved for 256 iterations; four
+                              restarts in a row without progress end with IHDG_ERR_MAXITER.  max_iters
                               caps the iterations; prec must be IHDG_FP64 (else IHDG_ERR_UNSUPPORTED).
                               The iHDG sweep as the Krylov operator is the use the paper suggests
                               for regimes where the plain iteration fails (end of Section 4)      */

@@ -1059,10 +1059,12 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
 }
 
 // BiCGStab (van der Vorst) on (I - T)u = c, the sweep T as the operator, in
-// FP64.  Each iteration: rho = (rhat, r) with |r|^2 in the same pass, p, v =
-// A p, (rhat, v), s, t = A s, (t, s) and (t, t) in one pass, then x and r in
-// one pass; the scalars stay in device memory (the update kernels read them),
-// so the host waits only at the convergence checks every kCheck iterations.
+// FP64.  Each iteration: p; v = A p as a sweep and one pass that also forms
+// (v, rhat); s; t = A s as a sweep and one pass that also forms (t, s) and
+// (t, t); x and r in one pass that also forms (r, rhat) and |r|^2 for the
+// next iteration.  The scalars stay in device memory (the update kernels read
+// them), so the host waits only at the convergence checks every kCheck
+// iterations.
 // When the recursive residual meets the tolerance, the true residual is
 // formed with one sweep; if it does not, the iteration restarts from u.
 static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
@@ -1081,13 +1083,6 @@ static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, doubl
   double* sc = part + (size_t)ihdg::kDotGroups * 2;    // 16 scalars
   double* u = c->u64[c->cur];
   double hsc[16];
-  // v_out = (I - T) v_in
-  auto apply = [&](const double* vin, double* vout) -> hipError_t {
-    hipError_t e = one_sweep(c, false, vin, vout, c->c64);
-    if (e != hipSuccess) return e;
-    c->stats.fp64_sweeps += 1;
-    return launch_kapply(vout, vin, c->c64, N, st);
-  };
   auto readsc = [&]() -> hipError_t {
     hipError_t e = hipMemcpyAsync(hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, st);
     return e == hipSuccess ? hipStreamSynchronize(st) : e;
@@ -1098,6 +1093,8 @@ static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, doubl
   bnorm = std::sqrt(std::max(hsc[7], 0.0));
   if (bnorm == 0.0) bnorm = 1.0;
   int64_t it = 0;
+  double true_best = INFINITY;
+  int no_gain = 0;  // restarts in a row whose true residual did not improve
   for (int restart = 0; restart < 1000; ++restart) {
     // true residual r = psi(u) - u = c - (I - T) u; rhat = r
     HIPCHK(c, one_sweep(c, false, u, r, c->c64));
@@ -1112,23 +1109,37 @@ static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, doubl
     if (!std::isfinite(rn)) return fail(c, IHDG_ERR_DIVERGED, "non-finite residual");
     if (rn <= tol * bnorm) return IHDG_OK;
     if (it >= c->opt.max_iters) return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
+    if (rn < 0.99 * true_best) {
+      true_best = rn;
+      no_gain = 0;
+    } else if (++no_gain >= 4) {
+      return fail(c, IHDG_ERR_MAXITER, "BiCGStab stagnated above the tolerance");
+    }
     // rho_1 = (rhat, r) and |r|^2 into the parity-1 slot
     int q = 1;
     HIPCHK(c, launch_kdots(r, rh, N, 2, c->wnorm, n_loc, part, sc + 8 + 2 * q, nullptr, 0, st));
     bool first = true, again = false;
+    // stagnation: the recursive residual has not improved by 1% for kStall
+    // iterations -> confirm with the true residual and restart from u
+    constexpr int64_t kStall = 256;
+    double rec_best = INFINITY;
+    int64_t it_best = it;
     while (it < c->opt.max_iters && !again) {
       const int n = (int)std::min<int64_t>(kCheck, c->opt.max_iters - it);
       for (int k = 0; k < n; ++k) {
         HIPCHK(c, launch_bicg_p(p, r, v, sc, q, first ? 1 : 0, N, st));
         first = false;
-        HIPCHK(c, apply(p, v));
-        HIPCHK(c, launch_kdots(v, rh, N, 1, c->wnorm, n_loc, part, sc + 2, nullptr, 0, st));
+        // v = (I - T) p and (v, rhat)
+        HIPCHK(c, one_sweep(c, false, p, v, c->c64));
+        HIPCHK(c, launch_bicg_apply_dot1(v, p, c->c64, rh, c->wnorm, n_loc, N, part, sc + 2, st));
         HIPCHK(c, launch_bicg_s(sv, r, v, sc, q, N, st));
-        HIPCHK(c, apply(sv, t));
-        HIPCHK(c, launch_kdots(t, sv, N, 2, c->wnorm, n_loc, part, sc + 5, nullptr, 0, st));
-        HIPCHK(c, launch_bicg_xr(u, r, p, sv, t, sc, N, st));
+        // t = (I - T) s, (t, s) and (t, t)
+        HIPCHK(c, one_sweep(c, false, sv, t, c->c64));
+        HIPCHK(c, launch_bicg_apply_dot2(t, sv, c->c64, c->wnorm, n_loc, N, part, sc + 5, st));
+        c->stats.fp64_sweeps += 2;
+        // x, r, then (r, rhat) and (r, r) for the next iteration
         q ^= 1;
-        HIPCHK(c, launch_kdots(r, rh, N, 2, c->wnorm, n_loc, part, sc + 8 + 2 * q, nullptr, 0, st));
+        HIPCHK(c, launch_bicg_xr_dot(u, r, p, sv, t, rh, sc, c->wnorm, n_loc, N, part, sc + 8 + 2 * q, st));
         ++it;
         c->stats.krylov_iters += 1;
       }
@@ -1140,6 +1151,12 @@ static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, doubl
       if (!std::isfinite(rr) || !std::isfinite(hsc[3]) || !std::isfinite(hsc[4]))
         return fail(c, IHDG_ERR_DIVERGED, "BiCGStab breakdown (non-finite scalar)");
       if (rel <= tol || hsc[8 + 2 * q] == 0.0) again = true;  // converged, or rho = 0: confirm / restart
+      if (rel < 0.99 * rec_best) {
+        rec_best = rel;
+        it_best = it;
+      } else if (it - it_best >= kStall) {
+        again = true;
+      }
     }
   }
   return fail(c, IHDG_ERR_MAXITER, "too many BiCGStab restarts");

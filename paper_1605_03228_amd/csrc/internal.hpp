@@ -155,7 +155,14 @@ hipError_t launch_scale_to_f32(float* out, const double* x, double scale, int64_
 hipError_t launch_bicg_p(double* p, const double* r, const double* v, const double* sc, int q, int first, int64_t n,
                          hipStream_t s);
 hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* sc, int q, int64_t n, hipStream_t s);
-hipError_t launch_bicg_xr(double* x, double* r, const double* p, const double* sv, const double* t, double* sc,
-                          int64_t n, hipStream_t s);
+// the producing passes with their dot products (partials over the kdots grid,
+// then the fixed-order final sum into out)
+hipError_t launch_bicg_apply_dot1(double* v, const double* p, const double* c, const double* rh, const double* w,
+                                  int n_loc, int64_t nvec, double* partial, double* out, hipStream_t s);
+hipError_t launch_bicg_apply_dot2(double* t, const double* sv, const double* c, const double* w, int n_loc,
+                                  int64_t nvec, double* partial, double* out, hipStream_t s);
+hipError_t launch_bicg_xr_dot(double* x, double* r, const double* p, const double* sv, const double* t,
+                              const double* rh, double* sc, const double* w, int n_loc, int64_t nvec, double* partial,
+                              double* out, hipStream_t s);
 
 }  // namespace ihdg

@@ -239,18 +239,98 @@ __global__ void k_bicg_s(double* __restrict__ s, const double* __restrict__ r, c
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     s[i] = r[i] - alpha * v[i];
 }
+// The passes that produce a vector also form its weighted dot products, as
+// partial sums per workgroup over the grid k_kdots_partial uses (G workgroups
+// of 256 threads, 2-entry chunks strided by G * 256), so k_kdots_final sums
+// them in the same fixed order.
+template <int K>
+__device__ __forceinline__ void block_partials(double (&acc)[K], double* __restrict__ partial) {
+  __shared__ double red[4][K];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    double t = acc[j];
+    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+    if (lane == 0) red[wv][j] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < K) {
+    const int j = threadIdx.x;
+    partial[(int64_t)blockIdx.x * K + j] = (red[0][j] + red[1][j]) + (red[2][j] + red[3][j]);
+  }
+}
+
+// v <- (p - v) + c: the operator (I - T) applied to p from v = psi(p); partial (v, rhat)
+__global__ __launch_bounds__(256) void k_bicg_apply_dot1(double* __restrict__ v, const double* __restrict__ p,
+                                                         const double* __restrict__ c,
+                                                         const double* __restrict__ rh,
+                                                         const double* __restrict__ w, int n_loc, int64_t nvec,
+                                                         double* __restrict__ partial) {
+  double acc[1] = {0.0};
+  const int64_t nch = nvec / 2, stride = (int64_t)gridDim.x * 256;
+  for (int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x; ch < nch; ch += stride) {
+    const int64_t o = ch * 2;
+    const double wr = w[(uint32_t)(o >> 6) % (uint32_t)n_loc];
+    const double2 pv = *(const double2*)(p + o), vv = *(const double2*)(v + o), cv = *(const double2*)(c + o),
+                  rv = *(const double2*)(rh + o);
+    double2 nv;
+    nv.x = (pv.x - vv.x) + cv.x;
+    nv.y = (pv.y - vv.y) + cv.y;
+    *(double2*)(v + o) = nv;
+    acc[0] += (wr * nv.x) * rv.x + (wr * nv.y) * rv.y;
+  }
+  block_partials<1>(acc, partial);
+}
+
+// t <- (s - t) + c; partials (t, s), (t, t)
+__global__ __launch_bounds__(256) void k_bicg_apply_dot2(double* __restrict__ t, const double* __restrict__ sv,
+                                                         const double* __restrict__ c,
+                                                         const double* __restrict__ w, int n_loc, int64_t nvec,
+                                                         double* __restrict__ partial) {
+  double acc[2] = {0.0, 0.0};
+  const int64_t nch = nvec / 2, stride = (int64_t)gridDim.x * 256;
+  for (int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x; ch < nch; ch += stride) {
+    const int64_t o = ch * 2;
+    const double wr = w[(uint32_t)(o >> 6) % (uint32_t)n_loc];
+    const double2 s2 = *(const double2*)(sv + o), t2 = *(const double2*)(t + o), c2 = *(const double2*)(c + o);
+    double2 nt;
+    nt.x = (s2.x - t2.x) + c2.x;
+    nt.y = (s2.y - t2.y) + c2.y;
+    *(double2*)(t + o) = nt;
+    acc[0] += (wr * nt.x) * s2.x + (wr * nt.y) * s2.y;
+    acc[1] += (wr * nt.x) * nt.x + (wr * nt.y) * nt.y;
+  }
+  block_partials<2>(acc, partial);
+}
+
 // omega = (t, s) / (t, t) (stored by one thread); x <- x + alpha p + omega s;
-// r <- s - omega t
-__global__ void k_bicg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ p,
-                          const double* __restrict__ s, const double* __restrict__ t, double* __restrict__ sc,
-                          int64_t n) {
+// r <- s - omega t; partials (r, rhat), (r, r)
+__global__ __launch_bounds__(256) void k_bicg_xr_dot(double* __restrict__ x, double* __restrict__ r,
+                                                     const double* __restrict__ p, const double* __restrict__ sv,
+                                                     const double* __restrict__ t, const double* __restrict__ rh,
+                                                     double* __restrict__ sc, const double* __restrict__ w,
+                                                     int n_loc, int64_t nvec, double* __restrict__ partial) {
   const double alpha = sc[3];
   const double omega = sc[6] != 0.0 ? sc[5] / sc[6] : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) sc[4] = omega;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i] + omega * s[i];
-    r[i] = s[i] - omega * t[i];
+  double acc[2] = {0.0, 0.0};
+  const int64_t nch = nvec / 2, stride = (int64_t)gridDim.x * 256;
+  for (int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x; ch < nch; ch += stride) {
+    const int64_t o = ch * 2;
+    const double wr = w[(uint32_t)(o >> 6) % (uint32_t)n_loc];
+    const double2 x2 = *(const double2*)(x + o), p2 = *(const double2*)(p + o), s2 = *(const double2*)(sv + o),
+                  t2 = *(const double2*)(t + o), h2 = *(const double2*)(rh + o);
+    double2 nx, nr;
+    nx.x = x2.x + (alpha * p2.x + omega * s2.x);
+    nx.y = x2.y + (alpha * p2.y + omega * s2.y);
+    nr.x = s2.x - omega * t2.x;
+    nr.y = s2.y - omega * t2.y;
+    *(double2*)(x + o) = nx;
+    *(double2*)(r + o) = nr;
+    acc[0] += (wr * nr.x) * h2.x + (wr * nr.y) * h2.y;
+    acc[1] += (wr * nr.x) * nr.x + (wr * nr.y) * nr.y;
   }
+  block_partials<2>(acc, partial);
 }
 
 // one workgroup per batch member: the same fixed-order reduction as k_reduce
@@ -402,9 +482,27 @@ hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* s
   hipLaunchKernelGGL(k_bicg_s, dim3(grid_for(n)), dim3(256), 0, s, sv, r, v, sc, q, n);
   return hipGetLastError();
 }
-hipError_t launch_bicg_xr(double* x, double* r, const double* p, const double* sv, const double* t, double* sc,
-                          int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_bicg_xr, dim3(grid_for(n)), dim3(256), 0, s, x, r, p, sv, t, sc, n);
+hipError_t launch_bicg_apply_dot1(double* v, const double* p, const double* c, const double* rh, const double* w,
+                                  int n_loc, int64_t nvec, double* partial, double* out, hipStream_t s) {
+  const int g = kdot_groups(nvec);
+  hipLaunchKernelGGL(k_bicg_apply_dot1, dim3((unsigned)g), dim3(256), 0, s, v, p, c, rh, w, n_loc, nvec, partial);
+  hipLaunchKernelGGL(k_kdots_final, dim3(1), dim3(256), 0, s, partial, g, 1, out, (double*)nullptr, 0);
+  return hipGetLastError();
+}
+hipError_t launch_bicg_apply_dot2(double* t, const double* sv, const double* c, const double* w, int n_loc,
+                                  int64_t nvec, double* partial, double* out, hipStream_t s) {
+  const int g = kdot_groups(nvec);
+  hipLaunchKernelGGL(k_bicg_apply_dot2, dim3((unsigned)g), dim3(256), 0, s, t, sv, c, w, n_loc, nvec, partial);
+  hipLaunchKernelGGL(k_kdots_final, dim3(2), dim3(256), 0, s, partial, g, 2, out, (double*)nullptr, 0);
+  return hipGetLastError();
+}
+hipError_t launch_bicg_xr_dot(double* x, double* r, const double* p, const double* sv, const double* t,
+                              const double* rh, double* sc, const double* w, int n_loc, int64_t nvec, double* partial,
+                              double* out, hipStream_t s) {
+  const int g = kdot_groups(nvec);
+  hipLaunchKernelGGL(k_bicg_xr_dot, dim3((unsigned)g), dim3(256), 0, s, x, r, p, sv, t, rh, sc, w, n_loc, nvec,
+                     partial);
+  hipLaunchKernelGGL(k_kdots_final, dim3(2), dim3(256), 0, s, partial, g, 2, out, (double*)nullptr, 0);
   return hipGetLastError();
 }
 hipError_t launch_kapply_linear(float* out, const float* v, int64_t n, hipStream_t s) {
