@@ -166,8 +166,10 @@ typedef struct {
   int32_t force_per_element; /* 1: per-element operators even where one could be shared      */
   int32_t block_waves;     /* launch shape of the sweep kernel: 0 = autotuned at setup (cached per
                               shape), 1/2/4/8 = waves per 64-element block, 3 = vector-FMA shared
-                              operator, 5 = transport with a shared operator on the matrix cores
-                              without LDS staging of the traces (2-D, 3-D p <= 3).  Other values:
+                              operator, 5 = transport (2-D, 3-D p <= 3) or convection-diffusion
+                              (2-D p <= 4, the face projection folded into the operator) with a
+                              shared operator on the matrix cores without LDS staging of the
+                              traces.  Other values:
                               IHDG_ERR_ARG; 3 or 5 where they do not apply: IHDG_ERR_UNSUPPORTED */
   int32_t time_stepping;   /* 1: keep what ihdg_time_step needs (shared operators only)               */
   int32_t transport_flux;  /* transport only: 0 = upwind HDG flux (eq. RiemannFluxBoth with |A| = |beta.n|),

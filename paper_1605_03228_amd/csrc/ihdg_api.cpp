@@ -343,7 +343,10 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
       if (!shared) return IHDG_ERR_UNSUPPORTED;
       break;
     case 5:
-      if (!shared || pde != IHDG_TRANSPORT || !ihdg::direct_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
+      if (!shared) return IHDG_ERR_UNSUPPORTED;
+      if (pde == IHDG_TRANSPORT && !ihdg::direct_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
+      if (pde == IHDG_CONVDIFF && !ihdg::direct_cd_supported(mi.p)) return IHDG_ERR_UNSUPPORTED;
+      if (pde == IHDG_SHALLOW_WATER) return IHDG_ERR_UNSUPPORTED;
       break;
     default: return IHDG_ERR_ARG;
   }
@@ -590,6 +593,7 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
   }
   std::vector<int> cand = c->shared ? std::vector<int>{4, 8, 3} : std::vector<int>{1, 2, 4, 8};
   if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::direct_supported(c->mi.dim, c->mi.p)) cand.push_back(5);
+  if (c->shared && c->pde == IHDG_CONVDIFF && ihdg::direct_cd_supported(c->mi.p)) cand.push_back(5);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   struct Events {  // destroyed on every return path
     hipEvent_t* a;

@@ -112,6 +112,8 @@ hipError_t launch_sweep_cd(int p, bool fp32, bool shared, int waves, const Sweep
 // True where the transport matrix-core variant without LDS staging (launch
 // shape 5, shared operators only) has an instance.
 bool direct_supported(int dim, int p);
+// the convection-diffusion direct kernel (launch shape 5, shared operator, 2-D) fits for order p
+bool direct_cd_supported(int p);
 
 hipError_t launch_sweep_batched_transport(int dim, int p, bool fp32, bool shared, int waves, const BatchDesc* d,
                                           const int* owner, int64_t nb, int sidx, hipStream_t s);

@@ -6,8 +6,9 @@ several 64-element blocks with a ragged last block:
 
 * per-element operators: 1, 2, 4, 8 waves per block;
 * shared operators: 4 and 8 waves (matrix cores, traces staged in LDS),
-  3 (vector FMA), 5 (transport only: matrix cores fed straight from the
-  iterate, no LDS staging).
+  3 (vector FMA), 5 (transport and convection-diffusion: matrix cores fed
+  straight from the iterate, no LDS staging; for convection-diffusion the
+  face projection is folded into the operator).
 
 Bar: one sweep is an affine map applied in FP64, so after a few sweeps the
 iterates agree with the oracle's to rounding (1e-12 relative in the h-norm);
@@ -18,6 +19,7 @@ import pytest
 import torch
 
 import workloads as w
+from oracle.convdiff import CDOperators
 from oracle.norms import h_norm
 from oracle.transport import TransportOperators
 
@@ -63,12 +65,24 @@ SHARED = [
 SHAPES = [(name, make, wv, {}) for name, make in SHARED for wv in (3, 4, 5, 8)]
 SHAPES += [("cfg2_13x11_p3_per_el", _ragged_cfg2, wv, {}) for wv in (1, 2, 4, 8)]
 SHAPES += [("3d_4cube_p4_shared", lambda: w.config3(n=4, p=4), wv, {}) for wv in (3, 4, 8)]
+CD_SHARED = [
+    ("cd_elliptic_19x13_p3", lambda: w.cd_elliptic((19, 13), 3, gamma=1.0, nu=1.0)),
+    ("cd_elliptic_9x11_p4", lambda: w.cd_elliptic((9, 11), 4, gamma=1.5, nu=2.0)),
+    ("cd_const_beta_17x9_p2", lambda: w.cd_poly((17, 9), 2, kappa=0.3, affine_beta=False)),
+    ("cd_const_beta_23x7_p1", lambda: w.cd_poly((23, 7), 1, kappa=1e-3, affine_beta=False)),
+    ("cd_const_beta_13x11_p3", lambda: w.cd_poly((13, 11), 3, kappa=1e-3, affine_beta=False)),
+]
+SHAPES += [(name, make, wv, {}) for name, make in CD_SHARED for wv in (3, 4, 5, 8)]
+
+
+def _oracle(pr):
+    return CDOperators(pr) if pr.pde == "cd" else TransportOperators(pr)
 
 
 @pytest.mark.parametrize("name,make,waves,kw", SHAPES, ids=[f"{c[0]}-w{c[2]}" for c in SHAPES])
 def test_launch_shape_per_sweep(name, make, waves, kw):
     pr = make()
-    o = TransportOperators(pr)
+    o = _oracle(pr)
     s = _solver(pr, block_waves=waves, **kw)
     assert s.stats()["kernel_waves"] == waves
     u = np.zeros((o.mesh.n_el, s.sz["n_loc"]))
@@ -81,20 +95,26 @@ def test_launch_shape_per_sweep(name, make, waves, kw):
     s.close()
 
 
-@pytest.mark.parametrize("name,make", [SHARED[1], SHARED[4]], ids=[SHARED[1][0], SHARED[4][0]])
+@pytest.mark.parametrize("name,make", [SHARED[1], SHARED[4], CD_SHARED[3], CD_SHARED[4]],
+                         ids=[SHARED[1][0], SHARED[4][0], CD_SHARED[3][0], CD_SHARED[4][0]])
 def test_direct_variant_mixed_precision_solve(name, make):
+    """Mixed solves on the direct variant, on problems where the plain
+    iteration converges (convection-dominated; the elliptic regime's mixed
+    solves, at a tighter tolerance, are in test_gpu_elliptic.py)."""
     pr = make()
-    o = TransportOperators(pr)
+    o = _oracle(pr)
     s = _solver(pr, block_waves=5, prec=1)
     res = s.solve(1e-10)
     assert res["status"] == 0, res
-    assert _rel(o, _u(s), o.downwind()) < 1e-8
+    ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
+    assert _rel(o, _u(s), ref) < 1e-8
     s.close()
 
 
 def test_direct_variant_batched_equals_single_bitwise():
     from paper_1605_03228_amd import Batch
-    items = [w.config3(n=5, p=3), w.transport_const((19, 13), 2, (1.0, 0.5)), w.config3(seed=2, n=6, p=3)]
+    items = [w.config3(n=5, p=3), w.transport_const((19, 13), 2, (1.0, 0.5)), w.config3(seed=2, n=6, p=3),
+             w.cd_poly((17, 9), 2, kappa=0.3, affine_beta=False), w.cd_elliptic((5, 7), 3, gamma=1.0, nu=1.0)]
     singles = []
     for pr in items:
         s = _solver(pr, block_waves=5)
@@ -120,8 +140,10 @@ def test_direct_variant_batched_equals_single_bitwise():
 
 def test_launch_shape_validation():
     from paper_1605_03228_amd.binding import IhdgError
-    cases = [(w.sw_standing_wave((6, 6), 2, f0=0.3), 5, 2),       # direct variant: transport only
+    cases = [(w.sw_standing_wave((6, 6), 2, f0=0.3), 5, 2),       # direct variant: not shallow water
              (w.config3(n=3, p=4), 5, 2),                         # operator too large for its LDS layout
+             (w.cd_elliptic((4, 4), 5, gamma=1.0), 5, 2),         # convection-diffusion: p <= 4
+             (w.cd_smooth((6, 5), 3, kappa=1e-2), 5, 2),          # per-element operators
              (_ragged_cfg2(), 3, 2),                              # vector-FMA shared variant, per-element operators
              (_ragged_cfg2(), 5, 2),
              (w.config1(), 6, 1), (w.config1(), -1, 1)]           # not a launch shape
