@@ -167,6 +167,32 @@ def test_bicgstab_rejects_mixed_and_unknown_method():
     assert st == 1
 
 
+@pytest.mark.parametrize("kw", [{"krylov": "bicgstab"}, {"krylov_restart": 10}, {"krylov_restart": 10, "prec": 1}],
+                         ids=["bicgstab", "gmres", "mixed_gmres"])
+def test_krylov_max_iters_reports_maxiter(kw):
+    """A Krylov solve stopped by max_iters reports IHDG_ERR_MAXITER (forced from
+    the host with a tiny cap) and leaves a finite iterate."""
+    pr = w.cd_smooth((8, 8), 4, kappa=1e-2)
+    s = gpu_solver(pr, max_iters=5, **kw)
+    res = s.solve(1e-12)
+    assert res["status"] == 7, res
+    assert res["krylov_iters"] <= 5 + 8
+    assert np.all(np.isfinite(gpu_u(s)))
+
+
+def test_batch_last_error_empty_after_clean_rounds():
+    from paper_1605_03228_amd import Batch
+    b = Batch(max_members=4)
+    b.add(gpu_solver(w.config2(n=9, p=3)), 1e-10, 0)
+    for _ in range(1000):
+        if b.round(16) == 0:
+            break
+    for r in b.poll():
+        r["solver"].close()
+    assert b.lib.ihdg_batch_last_error(b.h) == b""
+    b.close()
+
+
 def test_mixed_gmres_where_ihdg_diverges():
     """The same with prec = mixed: FP32 operators and basis inside each cycle,
     the FP64 residual at every restart; same tolerance, same bar."""
