@@ -106,7 +106,11 @@ class Server:
         per-request records and latency/throughput summaries."""
         pending = collections.deque(sorted(requests, key=lambda r: r[1]))
         waiting = collections.deque()
-        batch = Batch(self.max_members, self.max_blocks, self.device)
+        # Batch rounds are launched directly, not replayed from captured graphs:
+        # the Krylov and setup workers' synchronising calls can invalidate a
+        # capture taken meanwhile on this runtime, and replay saved no
+        # measurable time on batch rounds.
+        batch = Batch(self.max_members, self.max_blocks, self.device, use_graphs=False)
         pool = ThreadPoolExecutor(self.krylov_workers)
         setup_pool = ThreadPoolExecutor(self.setup_workers)
         futures = {}
