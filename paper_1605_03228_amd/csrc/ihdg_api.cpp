@@ -628,14 +628,14 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
     for (int i = 0; i < 2; ++i)
       if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, a, c->stream)) != hipSuccess)
         return e;
-    hipEventRecord(e0, c->stream);
+    if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) return e;
     for (int i = 0; i < reps; ++i)
       if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, a, c->stream)) != hipSuccess)
         return e;
-    hipEventRecord(e1, c->stream);
+    if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) return e;
     if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
     float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return e;
     if (ms < bestt) {
       bestt = ms;
       bw = w;
@@ -698,7 +698,7 @@ static hipError_t run_batch(ihdg_ctx* c, bool fp32, int n) {
     if (e != hipSuccess) return e;
     if (e2 != hipSuccess) return e2;
     e = hipGraphInstantiate(slot, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       *slot = nullptr;
       return e;
