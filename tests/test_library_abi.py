@@ -83,3 +83,54 @@ def test_mesh_limits(lib):
     assert s["n_el"] == 1 << 30
     s = b.sizes((1, 1), 6, b.CD)
     assert s["n_el"] == 1 and s["n_loc"] == 3 * 49 and s["n_in"] == 28
+
+
+def test_struct_layouts_match_the_header(lib, tmp_path):
+    """The ctypes mirrors of the option and coefficient structs have the sizes and
+    field offsets a C compiler gives the header's structs (checked with gcc)."""
+    import shutil
+    import subprocess
+    from paper_1605_03228_amd import binding as b
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    checks = {"ihdg_coeffs": (b.Coeffs, [f[0] for f in b.Coeffs._fields_]),
+              "ihdg_options": (b.Options, [f[0] for f in b.Options._fields_])}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ihdg.h"', "int main(void) {"]
+    for cname, (_, fields) in checks.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in fields:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "abi.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "abi"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, (cls, fields) in checks.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in fields:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def test_krylov_option_marshalling(lib):
+    from paper_1605_03228_amd import binding as b
+    o = b._options(krylov="bicgstab")
+    assert o.krylov_method == 1 and o.krylov_restart >= 1
+    o = b._options(krylov_restart=40)
+    assert o.krylov_method == 0 and o.krylov_restart == 40
+    o = b._options()
+    assert o.krylov_method == 0 and o.krylov_restart == 0
+    with pytest.raises(KeyError):
+        b._options(krylov="cg")
+
+
+def test_serving_routes_elliptic_and_diffusive_requests_to_krylov():
+    import workloads as w
+    from paper_1605_03228_amd.serving import needs_krylov
+    assert needs_krylov(w.cd_elliptic((8, 8), 2, gamma=1.0))
+    assert needs_krylov(w.config4b(eps=1e-2, n=8, p=2))
+    assert not needs_krylov(w.config4b(eps=1e-4, n=8, p=2))
+    assert not needs_krylov(w.config2(n=8, p=2))
