@@ -214,9 +214,10 @@ static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared
     L.off_cf = take(nvec * 8);
   }
   if (krylov > 0 && kmethod == 1) {
-    // BiCGStab: [rhat | r], [s | t], p, v; dot partials (kDotGroups x 2) and 16 scalars
+    // BiCGStab: [rhat | r], [s | t], p, v; two partial buffers (kDotGroups x 2
+    // each) and 16 scalars
     L.off_kry = take(nvec * 8 * 6);
-    L.off_krypart = take(((size_t)ihdg::kDotGroups * 2 + 16) * 8);
+    L.off_krypart = take(((size_t)ihdg::kDotGroups * 4 + 16) * 8);
   } else if (krylov > 0) {
     L.off_kry = take(nvec * (mixed ? 4 : 8) * (size_t)(krylov + 1));
     // dot partials (kDotGroups x (m+1)), Hessenberg columns ((m+1) x m), the
@@ -1066,9 +1067,10 @@ static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* 
 // FP64.  Each iteration: p; v = A p as a sweep and one pass that also forms
 // (v, rhat); s; t = A s as a sweep and one pass that also forms (t, s) and
 // (t, t); x and r in one pass that also forms (r, rhat) and |r|^2 for the
-// next iteration.  The scalars stay in device memory (the update kernels read
-// them), so the host waits only at the convergence checks every kCheck
-// iterations.
+// next iteration.  Each producing pass leaves workgroup partials that the
+// consuming pass sums itself, and the scalars stay in device memory, so an
+// iteration is 7 launches and the host waits only at the convergence checks
+// every kCheck iterations.
 // When the recursive residual meets the tolerance, the true residual is
 // formed with one sweep; if it does not, the iteration restarts from u.
 static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
@@ -1083,8 +1085,9 @@ static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, doubl
   double* t = B + 3 * N;
   double* p = B + 4 * N;
   double* v = B + 5 * N;
-  double* part = c->kry_part;                          // kDotGroups x 2
-  double* sc = part + (size_t)ihdg::kDotGroups * 2;    // 16 scalars
+  double* part = c->kry_part;                           // partials A: (v, rhat), then (r, rhat), (r, r)
+  double* partB = part + (size_t)ihdg::kDotGroups * 2;  // partials B: (t, s), (t, t)
+  double* sc = part + (size_t)ihdg::kDotGroups * 4;     // 16 scalars
   double* u = c->u64[c->cur];
   double hsc[16];
   auto readsc = [&]() -> hipError_t {
@@ -1131,22 +1134,26 @@ static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, doubl
     while (it < c->opt.max_iters && !again) {
       const int n = (int)std::min<int64_t>(kCheck, c->opt.max_iters - it);
       for (int k = 0; k < n; ++k) {
-        HIPCHK(c, launch_bicg_p(p, r, v, sc, q, first ? 1 : 0, N, st));
+        // p (rho from partials A of the last x/r pass, except first)
+        HIPCHK(c, launch_bicg_p(p, r, v, sc, part, q, first ? 1 : 0, N, st));
         first = false;
-        // v = (I - T) p and (v, rhat)
+        // v = (I - T) p and partials A of (v, rhat); s with alpha
         HIPCHK(c, one_sweep(c, false, p, v, c->c64));
-        HIPCHK(c, launch_bicg_apply_dot1(v, p, c->c64, rh, c->wnorm, n_loc, N, part, sc + 2, st));
-        HIPCHK(c, launch_bicg_s(sv, r, v, sc, q, N, st));
-        // t = (I - T) s, (t, s) and (t, t)
+        HIPCHK(c, launch_bicg_apply_dot1(v, p, c->c64, rh, c->wnorm, n_loc, N, part, st));
+        HIPCHK(c, launch_bicg_s(sv, r, v, sc, part, q, N, st));
+        // t = (I - T) s and partials B of (t, s), (t, t)
         HIPCHK(c, one_sweep(c, false, sv, t, c->c64));
-        HIPCHK(c, launch_bicg_apply_dot2(t, sv, c->c64, c->wnorm, n_loc, N, part, sc + 5, st));
+        HIPCHK(c, launch_bicg_apply_dot2(t, sv, c->c64, c->wnorm, n_loc, N, partB, st));
         c->stats.fp64_sweeps += 2;
-        // x, r, then (r, rhat) and (r, r) for the next iteration
+        // omega, x, r, and partials A of (r, rhat), (r, r) for the next iteration
         q ^= 1;
-        HIPCHK(c, launch_bicg_xr_dot(u, r, p, sv, t, rh, sc, c->wnorm, n_loc, N, part, sc + 8 + 2 * q, st));
+        HIPCHK(c, launch_bicg_xr_dot(u, r, p, sv, t, rh, sc, c->wnorm, n_loc, N, partB, part, st));
         ++it;
         c->stats.krylov_iters += 1;
       }
+      // the check: rho and |r|^2 of the last x/r pass into sc (the same sums
+      // the next p pass forms)
+      HIPCHK(c, launch_kdots_final(part, N, 2, sc + 8 + 2 * q, st));
       HIPCHK(c, readsc());
       const double rr = hsc[9 + 2 * q];  // |r|^2 after the last update
       const double rel = std::sqrt(std::max(rr, 0.0)) / bnorm;

@@ -153,18 +153,21 @@ hipError_t launch_kapply(double* out, const double* v, const double* c, int64_t 
 hipError_t launch_kapply_linear(float* out, const float* v, int64_t n, hipStream_t s);
 // out <- (float)(scale * x)
 hipError_t launch_scale_to_f32(float* out, const double* x, double scale, int64_t n, hipStream_t s);
-// BiCGStab updates with their scalars in device memory (layout in vector_ops.hip)
-hipError_t launch_bicg_p(double* p, const double* r, const double* v, const double* sc, int q, int first, int64_t n,
-                         hipStream_t s);
-hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* sc, int q, int64_t n, hipStream_t s);
-// the producing passes with their dot products (partials over the kdots grid,
-// then the fixed-order final sum into out)
+// BiCGStab passes with their scalars in device memory (layout in vector_ops.hip).
+// Each producing pass writes its dot products as workgroup partials (the
+// kdots grid); the consuming pass sums them itself.
+hipError_t launch_bicg_p(double* p, const double* r, const double* v, double* sc, const double* partial, int q,
+                         int first, int64_t nvec, hipStream_t s);
+hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* sc, const double* partial, int q,
+                         int64_t nvec, hipStream_t s);
 hipError_t launch_bicg_apply_dot1(double* v, const double* p, const double* c, const double* rh, const double* w,
-                                  int n_loc, int64_t nvec, double* partial, double* out, hipStream_t s);
+                                  int n_loc, int64_t nvec, double* partial, hipStream_t s);
 hipError_t launch_bicg_apply_dot2(double* t, const double* sv, const double* c, const double* w, int n_loc,
-                                  int64_t nvec, double* partial, double* out, hipStream_t s);
+                                  int64_t nvec, double* partial, hipStream_t s);
 hipError_t launch_bicg_xr_dot(double* x, double* r, const double* p, const double* sv, const double* t,
-                              const double* rh, double* sc, const double* w, int n_loc, int64_t nvec, double* partial,
-                              double* out, hipStream_t s);
+                              const double* rh, double* sc, const double* w, int n_loc, int64_t nvec,
+                              const double* tin, double* partial, hipStream_t s);
+// the fixed-order sums of k partials of the kdots grid for vectors of nvec entries
+hipError_t launch_kdots_final(const double* partial, int64_t nvec, int k, double* out, hipStream_t s);
 
 }  // namespace ihdg

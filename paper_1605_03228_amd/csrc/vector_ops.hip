@@ -218,26 +218,94 @@ __global__ void k_scale_to_f32(float* __restrict__ out, const double* __restrict
 // [2] (rhat, v), [3] alpha, [4] omega, [5] (t, s), [6] (t, t),
 // [8 + 2q] rho of iterations of parity q, [9 + 2q] the squared residual norm
 // computed with it.
+//
+// A kernel that needs a dot product sums the producing pass's G workgroup
+// partials itself: every workgroup forms the same sums, in the order
+// k_kdots_final uses (strided per thread, then a fixed tree), and workgroup 0
+// stores them in sc for the host and for later passes.
+template <int K>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partial, int groups, double (&out)[K]) {
+  __shared__ double red[K][256];
+  double a[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) a[j] = 0.0;
+  for (int g = threadIdx.x; g < groups; g += 256) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) a[j] += partial[(int64_t)g * K + j];
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) red[j][threadIdx.x] = a[j];
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+#pragma unroll
+      for (int j = 0; j < K; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < K; ++j) out[j] = red[j][0];
+  __syncthreads();  // red may be reused
+}
+
 // An exact zero in a denominator (the iteration has hit the solution, e.g. a
 // mesh without interior faces, where I - T = I) gives a zero scalar, so u stays
 // finite and the next convergence check sees r = 0.
+// rho_q and |r|^2 from the partials of the last x/r pass (unless first);
 // p <- r (first) or r + beta (p - omega v), beta = (rho_q / rho_{1-q}) (alpha / omega)
-__global__ void k_bicg_p(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ v,
-                         const double* __restrict__ sc, int q, int first, int64_t n) {
-  const double rp = sc[8 + 2 * (1 - q)], om0 = sc[4];
-  const double beta = (first || rp == 0.0 || om0 == 0.0) ? 0.0 : (sc[8 + 2 * q] / rp) * (sc[3] / om0);
-  const double om = sc[4];
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = first ? r[i] : r[i] + beta * (p[i] - om * v[i]);
+__global__ __launch_bounds__(256) void k_bicg_p(double* __restrict__ p, const double* __restrict__ r,
+                                                const double* __restrict__ v, double* __restrict__ sc,
+                                                const double* __restrict__ partial, int groups, int q, int first,
+                                                int64_t nvec) {
+  double rho = 0.0;
+  if (!first) {
+    double d[2];
+    sum_partials<2>(partial, groups, d);
+    rho = d[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[8 + 2 * q] = d[0];
+      sc[9 + 2 * q] = d[1];
+    }
+  }
+  const double rp = sc[8 + 2 * (1 - q)], om = sc[4];
+  const double beta = (first || rp == 0.0 || om == 0.0) ? 0.0 : (rho / rp) * (sc[3] / om);
+  const int64_t nch = nvec / 2, stride = (int64_t)gridDim.x * 256;
+  for (int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x; ch < nch; ch += stride) {
+    const int64_t o = ch * 2;
+    const double2 r2 = *(const double2*)(r + o);
+    double2 np;
+    if (first) {
+      np = r2;
+    } else {
+      const double2 p2 = *(const double2*)(p + o), v2 = *(const double2*)(v + o);
+      np.x = r2.x + beta * (p2.x - om * v2.x);
+      np.y = r2.y + beta * (p2.y - om * v2.y);
+    }
+    *(double2*)(p + o) = np;
+  }
 }
-// alpha = rho_q / (rhat, v) (stored by one thread; the others compute it too);
-// s <- r - alpha v
-__global__ void k_bicg_s(double* __restrict__ s, const double* __restrict__ r, const double* __restrict__ v,
-                         double* __restrict__ sc, int q, int64_t n) {
-  const double alpha = sc[2] != 0.0 ? sc[8 + 2 * q] / sc[2] : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc[3] = alpha;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    s[i] = r[i] - alpha * v[i];
+// (rhat, v) from the partials of the (I - T) p pass; alpha = rho_q / (rhat, v)
+// (both stored by workgroup 0); s <- r - alpha v
+__global__ __launch_bounds__(256) void k_bicg_s(double* __restrict__ s, const double* __restrict__ r,
+                                                const double* __restrict__ v, double* __restrict__ sc,
+                                                const double* __restrict__ partial, int groups, int q,
+                                                int64_t nvec) {
+  double d[1];
+  sum_partials<1>(partial, groups, d);
+  const double alpha = d[0] != 0.0 ? sc[8 + 2 * q] / d[0] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[2] = d[0];
+    sc[3] = alpha;
+  }
+  const int64_t nch = nvec / 2, stride = (int64_t)gridDim.x * 256;
+  for (int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x; ch < nch; ch += stride) {
+    const int64_t o = ch * 2;
+    const double2 r2 = *(const double2*)(r + o), v2 = *(const double2*)(v + o);
+    double2 ns;
+    ns.x = r2.x - alpha * v2.x;
+    ns.y = r2.y - alpha * v2.y;
+    *(double2*)(s + o) = ns;
+  }
 }
 // The passes that produce a vector also form its weighted dot products, as
 // partial sums per workgroup over the grid k_kdots_partial uses (G workgroups
@@ -303,16 +371,24 @@ __global__ __launch_bounds__(256) void k_bicg_apply_dot2(double* __restrict__ t,
   block_partials<2>(acc, partial);
 }
 
-// omega = (t, s) / (t, t) (stored by one thread); x <- x + alpha p + omega s;
-// r <- s - omega t; partials (r, rhat), (r, r)
+// (t, s) and (t, t) from the partials of the (I - T) s pass (tin); omega =
+// (t, s) / (t, t) (stored with them by workgroup 0); x <- x + alpha p + omega s;
+// r <- s - omega t; partials (r, rhat), (r, r) into partial
 __global__ __launch_bounds__(256) void k_bicg_xr_dot(double* __restrict__ x, double* __restrict__ r,
                                                      const double* __restrict__ p, const double* __restrict__ sv,
                                                      const double* __restrict__ t, const double* __restrict__ rh,
                                                      double* __restrict__ sc, const double* __restrict__ w,
-                                                     int n_loc, int64_t nvec, double* __restrict__ partial) {
+                                                     int n_loc, int64_t nvec, const double* __restrict__ tin,
+                                                     double* __restrict__ partial) {
+  double d[2];
+  sum_partials<2>(tin, (int)gridDim.x, d);
   const double alpha = sc[3];
-  const double omega = sc[6] != 0.0 ? sc[5] / sc[6] : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc[4] = omega;
+  const double omega = d[1] != 0.0 ? d[0] / d[1] : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[4] = omega;
+    sc[5] = d[0];
+    sc[6] = d[1];
+  }
   double acc[2] = {0.0, 0.0};
   const int64_t nch = nvec / 2, stride = (int64_t)gridDim.x * 256;
   for (int64_t ch = (int64_t)blockIdx.x * 256 + threadIdx.x; ch < nch; ch += stride) {
@@ -473,36 +549,41 @@ hipError_t launch_knormalize(float* v, int64_t n, const double* nn, double* hn, 
   hipLaunchKernelGGL(k_knormalize<float>, dim3(grid_for(n)), dim3(256), 0, s, v, n, nn, hn);
   return hipGetLastError();
 }
-hipError_t launch_bicg_p(double* p, const double* r, const double* v, const double* sc, int q, int first, int64_t n,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_bicg_p, dim3(grid_for(n)), dim3(256), 0, s, p, r, v, sc, q, first, n);
+hipError_t launch_bicg_p(double* p, const double* r, const double* v, double* sc, const double* partial, int q,
+                         int first, int64_t nvec, hipStream_t s) {
+  const int g = kdot_groups(nvec);
+  hipLaunchKernelGGL(k_bicg_p, dim3((unsigned)g), dim3(256), 0, s, p, r, v, sc, partial, g, q, first, nvec);
   return hipGetLastError();
 }
-hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* sc, int q, int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_bicg_s, dim3(grid_for(n)), dim3(256), 0, s, sv, r, v, sc, q, n);
+hipError_t launch_bicg_s(double* sv, const double* r, const double* v, double* sc, const double* partial, int q,
+                         int64_t nvec, hipStream_t s) {
+  const int g = kdot_groups(nvec);
+  hipLaunchKernelGGL(k_bicg_s, dim3((unsigned)g), dim3(256), 0, s, sv, r, v, sc, partial, g, q, nvec);
   return hipGetLastError();
 }
 hipError_t launch_bicg_apply_dot1(double* v, const double* p, const double* c, const double* rh, const double* w,
-                                  int n_loc, int64_t nvec, double* partial, double* out, hipStream_t s) {
+                                  int n_loc, int64_t nvec, double* partial, hipStream_t s) {
   const int g = kdot_groups(nvec);
   hipLaunchKernelGGL(k_bicg_apply_dot1, dim3((unsigned)g), dim3(256), 0, s, v, p, c, rh, w, n_loc, nvec, partial);
-  hipLaunchKernelGGL(k_kdots_final, dim3(1), dim3(256), 0, s, partial, g, 1, out, (double*)nullptr, 0);
   return hipGetLastError();
 }
 hipError_t launch_bicg_apply_dot2(double* t, const double* sv, const double* c, const double* w, int n_loc,
-                                  int64_t nvec, double* partial, double* out, hipStream_t s) {
+                                  int64_t nvec, double* partial, hipStream_t s) {
   const int g = kdot_groups(nvec);
   hipLaunchKernelGGL(k_bicg_apply_dot2, dim3((unsigned)g), dim3(256), 0, s, t, sv, c, w, n_loc, nvec, partial);
-  hipLaunchKernelGGL(k_kdots_final, dim3(2), dim3(256), 0, s, partial, g, 2, out, (double*)nullptr, 0);
   return hipGetLastError();
 }
 hipError_t launch_bicg_xr_dot(double* x, double* r, const double* p, const double* sv, const double* t,
-                              const double* rh, double* sc, const double* w, int n_loc, int64_t nvec, double* partial,
-                              double* out, hipStream_t s) {
+                              const double* rh, double* sc, const double* w, int n_loc, int64_t nvec,
+                              const double* tin, double* partial, hipStream_t s) {
   const int g = kdot_groups(nvec);
-  hipLaunchKernelGGL(k_bicg_xr_dot, dim3((unsigned)g), dim3(256), 0, s, x, r, p, sv, t, rh, sc, w, n_loc, nvec,
+  hipLaunchKernelGGL(k_bicg_xr_dot, dim3((unsigned)g), dim3(256), 0, s, x, r, p, sv, t, rh, sc, w, n_loc, nvec, tin,
                      partial);
-  hipLaunchKernelGGL(k_kdots_final, dim3(2), dim3(256), 0, s, partial, g, 2, out, (double*)nullptr, 0);
+  return hipGetLastError();
+}
+hipError_t launch_kdots_final(const double* partial, int64_t nvec, int k, double* out, hipStream_t s) {
+  const int g = kdot_groups(nvec);
+  hipLaunchKernelGGL(k_kdots_final, dim3((unsigned)k), dim3(256), 0, s, partial, g, k, out, (double*)nullptr, 0);
   return hipGetLastError();
 }
 hipError_t launch_kapply_linear(float* out, const float* v, int64_t n, hipStream_t s) {
