@@ -86,15 +86,17 @@ def test_mesh_limits(lib):
 
 
 def test_struct_layouts_match_the_header(lib, tmp_path):
-    """The ctypes mirrors of the option and coefficient structs have the sizes and
-    field offsets a C compiler gives the header's structs (checked with gcc)."""
+    """Every ctypes mirror of a header struct has the size and field offsets a C
+    compiler gives it (checked with gcc): a mirror smaller than the struct would
+    let the library write past a buffer the binding allocated."""
     import shutil
     import subprocess
     from paper_1605_03228_amd import binding as b
     if shutil.which("gcc") is None:
         pytest.skip("no gcc")
-    checks = {"ihdg_coeffs": (b.Coeffs, [f[0] for f in b.Coeffs._fields_]),
-              "ihdg_options": (b.Options, [f[0] for f in b.Options._fields_])}
+    mirrors = {"ihdg_mesh": b.Mesh, "ihdg_sizes_t": b.Sizes, "ihdg_coeffs": b.Coeffs,
+               "ihdg_options": b.Options, "ihdg_stats": b.Stats, "ihdg_batch_result": b.BatchResult}
+    checks = {cname: (cls, [f[0] for f in cls._fields_]) for cname, cls in mirrors.items()}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "ihdg.h"', "int main(void) {"]
     for cname, (_, fields) in checks.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
