@@ -17,11 +17,12 @@ oracle's own throughput on the host.
 Other workloads (--workload): cfg1 (8x8 p=2 transport, constant beta),
 cfg3 (64^3 p=3 transport, constant beta: shared operator on MFMA), cfg4a
 (128^2 p=3 linearised shallow water, one Crank-Nicolson step), cfg4b
-(128^2 p=4 convection-diffusion, eps = 1e-4), elliptic (p=3, beta = 0,
-kappa = 1, nu = 1 with the mesh-dependent tau* = (p+1)(p+2)/h: sweep rate on
-512^2, and on 128^2, where the plain iteration is already too slow, time to
-tolerance with GMRES on the iHDG operator), serve and batch.  The default line
-is cfg2.
+(128^2 p=4 convection-diffusion, eps = 1e-4; the same line times the Krylov
+solvers on the same mesh at eps = 1e-2, where the plain iteration diverges),
+elliptic (p=3, beta = 0, kappa = 1, nu = 1 with the mesh-dependent
+tau* = (p+1)(p+2)/h: sweep rate on 512^2, and on 128^2, where the plain
+iteration is already too slow, time to tolerance with GMRES and BiCGStab on
+the iHDG operator), serve and batch.  The default line is cfg2.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2] [--no-oracle]
 """
@@ -96,7 +97,8 @@ def make_problem(name):
             "cfg3": lambda: w.config3(seed=0), "cfg4a": lambda: w.config4a(seed=0),
             "cfg4b": lambda: w.config4b(eps=1e-4),
             "elliptic": lambda: w.cd_elliptic((512, 512), 3, gamma=1.0, nu=1.0),
-            "elliptic_solve": lambda: w.cd_elliptic((128, 128), 3, gamma=1.0, nu=1.0)}[name]()
+            "elliptic_solve": lambda: w.cd_elliptic((128, 128), 3, gamma=1.0, nu=1.0),
+            "cfg4b_krylov": lambda: w.config4b(eps=1e-2)}[name]()
 
 
 DESCR = {"cfg1": "2-D steady transport 8x8 quads p=2, beta=(1,0.5), shared operator",
@@ -424,6 +426,44 @@ def elliptic(args):
     print(json.dumps(line), flush=True)
 
 
+def cd_krylov_legs(torch, dev, tol, no_oracle):
+    """Config 4b at eps = 1e-2, where the plain iteration diverges: the plain
+    FP64 solve (expected to stop diverged), GMRES(100) in FP64 and mixed, and
+    BiCGStab, each from zero to the same relative residual, with its error
+    against the oracle's direct solve."""
+    from paper_1605_03228_amd.problem_io import make_solver
+    pr = make_problem("cfg4b_krylov")
+    legs = {}
+    for name, opts in (("plain_fp64", {"max_iters": 20000}),
+                       ("gmres100_fp64", {"krylov_restart": 100, "max_iters": 200000}),
+                       ("gmres100_mixed", {"krylov_restart": 100, "max_iters": 200000, "prec": 1}),
+                       ("bicgstab_fp64", {"krylov": "bicgstab", "max_iters": 200000})):
+        t0 = time.perf_counter()
+        s = make_solver(pr, device=dev, **opts)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        r = s.solve(tol)
+        torch.cuda.synchronize()
+        legs[name] = {"setup_s": setup, "time_to_tol_s": time.perf_counter() - t0, "status": r["status"],
+                      "krylov_iters": r["krylov_iters"], "fp64_sweeps": r["fp64_sweeps"],
+                      "fp32_sweeps": r["fp32_sweeps"], "u": s.get_solution()}
+        s.close()
+    if not no_oracle:
+        from oracle.convdiff import CDOperators
+        from oracle.norms import h_norm
+        o = CDOperators(pr)
+        ref = o.direct_hdg()
+        nr = h_norm(o.mesh, o.el, ref)
+        for leg in legs.values():
+            a = leg["u"].reshape(ref.shape).cpu().numpy()
+            leg["rel_err_vs_oracle"] = h_norm(o.mesh, o.el, a - ref) / nr if np.isfinite(a).all() else None
+    for leg in legs.values():
+        del leg["u"]
+    return {"workload": "2-D convection-diffusion 128x128 p=4, eps=1e-2, beta=(1+y,1+x), per-element local "
+                        "operators", "solve_tol": tol, "legs": legs}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -519,6 +559,9 @@ def main():
                         "sweeps": (rn["iters"] if prec == 0 else rn["fp32_sweeps"] + rn["fp64_sweeps"])}
             sn.close()
 
+    # ---- config 4b: the Krylov wrapper at eps = 1e-2, where the plain iteration diverges
+    krylov = cd_krylov_legs(torch, dev, tol, args.no_oracle) if args.workload == "cfg4b" else None
+
     err64 = errmx = None
     cpu = None
     if not args.no_oracle:
@@ -569,6 +612,7 @@ def main():
                   "fp32_sweep_rate": fp32_rate, "rel_err_vs_oracle": errmx,
                   "speedup_time_to_tol_vs_fp64": (ttt64 / tttmx) if tttmx > 0 else None},
         "npc_flux": ({k: {kk: vv for kk, vv in v.items() if kk != "u"} for k, v in npc.items()} if npc else None),
+        "krylov_eps_1e-2": krylov,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
