@@ -2,7 +2,8 @@
 // staging of the traces ("direct" variant, launch shape 5).
 //
 // The sweep of Section 3 (one application of u <- c_K + G x_K(u) to every
-// element, eq. (16) with the upwind selection of eq. (15)) for a constant
+// element, eqs. transportLocalk1 / transportLocale with the upwind selection
+// of eq. uhk) for a constant
 // operator G (n_loc x n_in) is a GEMM  U' = G X + C  whose columns are the
 // elements.  The LDS variant first gathers the traces X of a 64-element block
 // into LDS and synchronises before the MFMA chain.  Here the gather feeds the
