@@ -147,7 +147,8 @@ KRYLOV_CASES = [("transport_9x9_p3_per_element", lambda: w.config2(n=9, p=3)),
                 ("cd_7x9_p3_eps1e-3", lambda: w.cd_smooth((7, 9), 3, kappa=1e-3))]
 
 
-@pytest.mark.parametrize("kw", [{"krylov": "bicgstab"}, {"krylov_restart": 20}], ids=["bicgstab", "gmres"])
+@pytest.mark.parametrize("kw", [{"krylov": "bicgstab"}, {"krylov_restart": 20}, {"krylov_restart": 20, "prec": 1}],
+                         ids=["bicgstab", "gmres", "mixed_gmres"])
 @pytest.mark.parametrize("name,make", KRYLOV_CASES, ids=[c[0] for c in KRYLOV_CASES])
 def test_krylov_across_pdes_and_ragged_blocks(name, make, kw):
     """The Krylov solvers apply (I - T) through every PDE's sweep kernel, per-element
@@ -162,6 +163,28 @@ def test_krylov_across_pdes_and_ragged_blocks(name, make, kw):
     err = rel(o, gpu_u(s), ref)
     print(f"  {name}: {res['krylov_iters']} iterations, {res['fp64_sweeps']} sweeps, rel err {err:.2e}", flush=True)
     assert err < 1e-9
+
+
+def test_batch_rejects_krylov_contexts():
+    """A batch advances members by plain sweeps only: a context set up for a
+    Krylov solve is refused (IHDG_ERR_UNSUPPORTED) and the batch stays usable."""
+    from paper_1605_03228_amd import Batch, binding
+    b = Batch(max_members=2)
+    for kw in ({"krylov": "bicgstab"}, {"krylov_restart": 10}):
+        s = gpu_solver(w.cd_smooth((4, 4), 2, kappa=1e-2), **kw)
+        with pytest.raises(binding.IhdgError) as e:
+            b.add(s, 1e-10, 1)
+        assert e.value.status == 2
+        s.close()
+    s = gpu_solver(w.config2(n=5, p=2))
+    b.add(s, 1e-10, 0)
+    for _ in range(1000):
+        if b.round(16) == 0:
+            break
+    res = b.poll()
+    assert [r["status"] for r in res] == [0]
+    s.close()
+    b.close()
 
 
 def test_bicgstab_rejects_mixed_and_unknown_method():
