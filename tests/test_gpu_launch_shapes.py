@@ -111,6 +111,23 @@ def test_direct_variant_mixed_precision_solve(name, make):
     s.close()
 
 
+@pytest.mark.parametrize("waves", [3, 4, 5, 8])
+def test_bicgstab_on_every_cd_shared_shape(waves):
+    """BiCGStab applies (I - T) through the launch shape it is given, the direct
+    kernel with the face projection folded into the operator included: on the
+    elliptic regime (tau*) every shape reaches the oracle's direct solve."""
+    pr = CD_SHARED[0][1]()
+    o = _oracle(pr)
+    s = _solver(pr, block_waves=waves, krylov="bicgstab", max_iters=20000)
+    assert s.stats()["kernel_waves"] == waves
+    res = s.solve(1e-12)
+    assert res["status"] == 0, res
+    err = _rel(o, _u(s), o.direct_hdg())
+    print(f"  bicgstab w{waves}: {res['krylov_iters']} iterations, rel err {err:.2e}", flush=True)
+    assert err < 1e-8
+    s.close()
+
+
 def test_direct_variant_batched_equals_single_bitwise():
     from paper_1605_03228_amd import Batch
     items = [w.config3(n=5, p=3), w.transport_const((19, 13), 2, (1.0, 0.5)), w.config3(seed=2, n=6, p=3),
