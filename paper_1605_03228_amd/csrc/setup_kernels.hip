@@ -290,24 +290,45 @@ __device__ double entry_F(const SetupArgs& a, const Basis& b, const ElemData& d,
 
 // Gauss-Jordan with partial pivoting on an n x ncol row-major matrix in global
 // memory; afterwards columns n..ncol-1 hold L^{-1} times the right-hand sides.
+// The pivot of column k is the first row i >= k of largest |A(i, k)| (rows
+// whose entry is NaN are never chosen; row k is kept if its own entry is NaN),
+// found by the first wave; the elimination updates one row per wave, 64
+// columns at a time.
 __device__ void gauss_jordan(double* A, int n, int ncol, int* flag) {
   __shared__ double colk[kMaxNloc];
   __shared__ int piv;
   __shared__ double pval;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  constexpr int kWaves = kST / 64;
   for (int k = 0; k < n; ++k) {
-    if (threadIdx.x == 0) {
-      int best = k;
-      double bv = fabs(A[(int64_t)k * ncol + k]);
-      for (int i = k + 1; i < n; ++i) {
-        double v = fabs(A[(int64_t)i * ncol + k]);
-        if (v > bv) {
+    if (wv == 0) {
+      int best = -1;
+      double bv = 0.0;
+      for (int i = k + lane; i < n; i += 64) {
+        const double v = fabs(A[(int64_t)i * ncol + k]);
+        if (best < 0 ? !isnan(v) : v > bv) {
           bv = v;
           best = i;
         }
       }
-      piv = best;
-      pval = A[(int64_t)best * ncol + k];
-      if (!(bv > 1e-300) || !isfinite(bv)) atomicOr(flag, 1);
+      for (int off = 32; off >= 1; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, 64);
+        const int oi = __shfl_xor(best, off, 64);
+        if (oi >= 0 && (best < 0 || ov > bv || (ov == bv && oi < best))) {
+          bv = ov;
+          best = oi;
+        }
+      }
+      if (lane == 0) {
+        const double vk = fabs(A[(int64_t)k * ncol + k]);
+        if (best < 0 || isnan(vk)) {
+          best = k;
+          bv = vk;
+        }
+        piv = best;
+        pval = A[(int64_t)best * ncol + k];
+        if (!(bv > 1e-300) || !isfinite(bv)) atomicOr(flag, 1);
+      }
     }
     __syncthreads();
     const int pr = piv;
@@ -323,10 +344,12 @@ __device__ void gauss_jordan(double* A, int n, int ncol, int* flag) {
     for (int j = k + threadIdx.x; j < ncol; j += blockDim.x) A[(int64_t)k * ncol + j] *= inv;
     for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = A[(int64_t)i * ncol + k];
     __syncthreads();
-    const int w = ncol - k;
-    for (int idx = threadIdx.x; idx < n * w; idx += blockDim.x) {
-      int i = idx / w, j = k + idx % w;
-      if (i != k) A[(int64_t)i * ncol + j] -= colk[i] * A[(int64_t)k * ncol + j];
+    const double* __restrict__ rk = A + (int64_t)k * ncol;
+    for (int i = wv; i < n; i += kWaves) {
+      if (i == k) continue;
+      double* __restrict__ ri = A + (int64_t)i * ncol;
+      const double ci = colk[i];
+      for (int j = k + lane; j < ncol; j += 64) ri[j] -= ci * rk[j];
     }
     __syncthreads();
   }
