@@ -7,7 +7,8 @@
 * transport with tangential flow (beta . n = 0 on every face normal to one
   axis) and without reaction (sigma = 0);
 * zero data (f = 0, g = 0): the solution is exactly zero and the relative
-  stopping test 0 <= tol * 0 must still end the solve.
+  stopping test 0 <= tol * 0 must still end the solve;
+* a local problem the elimination cannot factor is reported, not returned.
 
 Bar: per-sweep iterates agree with the oracle's to 1e-12 (relative, h-norm)
 and converged solutions to 1e-10.
@@ -119,4 +120,25 @@ def test_zero_data_gives_zero_solution(make, prec):
     assert res["status"] == 0, res
     assert res["iters"] <= 64
     assert np.all(_u(s) == 0.0)
+    s.close()
+
+
+@pytest.mark.parametrize("case", ["per_element", "shared"])
+def test_non_finite_local_problem_is_reported_singular(case):
+    """A local matrix the elimination cannot factor (here: NaN reaction, on one
+    element of a per-element problem or on the shared operator) ends ihdg_setup
+    with IHDG_ERR_SINGULAR_LOCAL, and the library stays usable."""
+    from paper_1605_03228_amd import binding
+    if case == "per_element":
+        pr = w.config2(n=5, p=2)
+        sig = pr.sigma_of_elements().copy()
+        sig[7] = np.nan
+        pr = w.Problem(**{**pr.__dict__, "sigma_el": sig})
+    else:
+        pr = w.transport_const((6, 6), 2, (1.0, 0.5), sigma=float("nan"))
+    with pytest.raises(binding.IhdgError) as e:
+        _solver(pr)
+    assert e.value.status == 5
+    s = _solver(w.config2(n=5, p=2))
+    assert s.solve(1e-10)["status"] == 0
     s.close()
