@@ -8,7 +8,8 @@
   axis) and without reaction (sigma = 0);
 * zero data (f = 0, g = 0): the solution is exactly zero and the relative
   stopping test 0 <= tol * 0 must still end the solve;
-* a local problem the elimination cannot factor is reported, not returned.
+* a local problem the elimination cannot factor is reported, not returned;
+* caller-owned buffers below the footprint are refused.
 
 Bar: per-sweep iterates agree with the oracle's to 1e-12 (relative, h-norm)
 and converged solutions to 1e-10.
@@ -142,3 +143,50 @@ def test_non_finite_local_problem_is_reported_singular(case):
     s = _solver(w.config2(n=5, p=2))
     assert s.solve(1e-10)["status"] == 0
     s.close()
+
+
+def test_buffers_smaller_than_the_footprint_are_refused():
+    """Caller-owned memory below what the footprint queries report is refused
+    with IHDG_ERR_NOMEM before any device work: the context's workspace and
+    setup scratch, the batch's workspace, a full batch and a batch without room
+    for another member's blocks."""
+    import ctypes as C
+    from paper_1605_03228_amd import Batch, binding
+    from paper_1605_03228_amd.problem_io import coefficients
+    lib = binding.load()
+    pr = w.config2(n=9, p=3)                      # 81 elements: 2 blocks
+    cf = binding._coeffs(coefficients(pr, "cuda", None))
+    o = binding._options()
+    mesh = binding._mesh(pr.n, None, None)
+    pb, sb = C.c_size_t(), C.c_size_t()
+    assert lib.ihdg_footprint(C.byref(mesh), pr.p, binding.TRANSPORT, C.byref(cf), C.byref(o), C.byref(pb),
+                              C.byref(sb)) == 0
+    ws = torch.empty(pb.value, dtype=torch.uint8, device="cuda")
+    scr = torch.empty(sb.value, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    per_element = (pr.p + 1) ** 2 * ((pr.p + 1) ** 2 + 4 * (pr.p + 1) + 1) * 8
+    for wsb, scb in ((pb.value - 256, sb.value), (pb.value, per_element - 8)):
+        ctx = C.c_void_p()
+        print(f"[gpu] setup with workspace {wsb} of {pb.value}, scratch {scb} of {sb.value}", flush=True)
+        st = lib.ihdg_setup(C.byref(mesh), pr.p, binding.TRANSPORT, C.byref(cf), C.byref(o),
+                            C.c_void_p(ws.data_ptr()), wsb, C.c_void_p(scr.data_ptr()), scb, None, C.byref(ctx))
+        assert st == 3, (wsb, scb, st)
+    nb = C.c_size_t()
+    assert lib.ihdg_batch_footprint(4, 64, C.byref(nb)) == 0
+    bws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    h = C.c_void_p()
+    assert lib.ihdg_batch_create(4, 64, C.c_void_p(bws.data_ptr()), nb.value - 8, None, C.byref(h)) == 3
+    s1, s2 = _solver(pr), _solver(pr)
+    full = Batch(max_members=1)
+    full.add(s1, 1e-10, 0)
+    with pytest.raises(binding.IhdgError) as e:
+        full.add(s2, 1e-10, 1)
+    assert e.value.status == 3
+    full.close()
+    narrow = Batch(max_members=4, max_blocks=1)
+    with pytest.raises(binding.IhdgError) as e:
+        narrow.add(s2, 1e-10, 0)
+    assert e.value.status == 3
+    narrow.close()
+    s1.close()
+    s2.close()
