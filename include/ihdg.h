@@ -324,14 +324,31 @@ typedef struct {
   int32_t iters;      /* sweeps done (FP64 + FP32)                                */
   double final_rel;   /* last relative increment (FP64) or FP64 defect (mixed)    */
 } ihdg_batch_result;
+/* IHDG_ERR_ARG if max_members < 1, max_blocks < 1 or bytes is NULL.  No device work. */
 ihdg_status ihdg_batch_footprint(int32_t max_members, int64_t max_blocks, size_t* bytes);
+/* workspace: caller-owned device memory, 256-byte aligned, at least the footprint
+ * (`bytes`), kept until ihdg_batch_destroy.  stream: the HIP stream of all batch
+ * work (NULL: the null stream, whose rounds are never graph-captured).  *out is a
+ * library-owned host object.  IHDG_ERR_ARG: NULL or misaligned workspace, NULL
+ * out, max_members or max_blocks < 1; IHDG_ERR_NOMEM: bytes below the footprint. */
 ihdg_status ihdg_batch_create(int32_t max_members, int64_t max_blocks, void* workspace, size_t bytes, void* stream,
                               ihdg_batch** out);
-/* Join the active set from the context's current iterate, to tolerance tol. */
+/* Join the active set from the context's current iterate, to tolerance tol > 0;
+ * tag is returned by ihdg_batch_poll.  Resets the context's statistics.
+ * IHDG_ERR_ARG: NULL b or ctx, tol <= 0, ctx already a member; IHDG_ERR_NOMEM:
+ * max_members members already, or the members' 64-element blocks would exceed
+ * max_blocks; IHDG_ERR_UNSUPPORTED: a context set up for a Krylov solve
+ * (krylov_restart > 0), which a batch does not advance.  No device work. */
 ihdg_status ihdg_batch_add(ihdg_batch* b, ihdg_ctx* ctx, double tol, int64_t tag);
-/* One round; n_active (nullable) receives the number of members still active. */
+/* One round of `sweeps` >= 1 sweeps (else IHDG_ERR_ARG); n_active (nullable)
+ * receives the number of members still active.  Synchronises the batch stream
+ * (it reads every member's norms).  A failing HIP call gives IHDG_ERR_HIP, named
+ * by ihdg_batch_last_error. */
 ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active);
-/* Results of members that finished since the last poll (at most max_out). */
+/* Results of members that finished since the last poll, at most max_out of them
+ * into the caller's array out (NULL allowed when max_out is 0); *n_out receives
+ * their number, and results beyond max_out stay for the next poll.
+ * IHDG_ERR_ARG: NULL b or n_out, or NULL out with max_out > 0. */
 ihdg_status ihdg_batch_poll(ihdg_batch* b, ihdg_batch_result* out, int32_t max_out, int32_t* n_out);
 /* Rounds replay a HIP graph of their launches (all groups' sweeps and the norm
  * reduction), captured when the round's structure (groups, their block counts,
@@ -342,6 +359,8 @@ ihdg_status ihdg_batch_use_graphs(ihdg_batch* b, int32_t enable);
 /* The HIP call that last failed in a batch call (its name and the runtime's
  * error name), for IHDG_ERR_HIP; "" if none.  Owned by the batch. */
 const char* ihdg_batch_last_error(const ihdg_batch* b);
+/* Frees the batch object and its captured graph (NULL allowed).  The caller
+ * then frees the workspace, and destroys the member contexts itself. */
 void ihdg_batch_destroy(ihdg_batch* b);
 
 const char* ihdg_last_error(const ihdg_ctx* ctx);
