@@ -223,15 +223,27 @@ ihdg_status ihdg_footprint(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde,
                            size_t* persistent_bytes, size_t* scratch_bytes);
 
 /*
- * Assemble every local HDG operator, factor it (LU with partial pivoting, FP64,
- * on the GPU), and store G_K = L_K^{-1} E_K and c_K = L_K^{-1} F_K, so that a
- * sweep is u_K^{k+1} = c_K + G_K x_K(u^k) (the local solve of eq. iHDGlocal
- * with the weighted trace of eq. iHDGtrace as its input x_K).  The initial
- * iterate is u^0 = 0.  `workspace` and `scratch` are device buffers of at
- * least the ihdg_footprint sizes, 256-byte aligned.  `stream` is a
- * hipStream_t.  Synchronises the stream (it checks for setup errors).
- * Returns IHDG_ERR_UNSUPPORTED for an interior transport face on which beta.n
- * changes sign.
+ * Assemble every local HDG operator and reduce it by Gauss-Jordan elimination
+ * with partial pivoting (FP64, on the GPU) to G_K = L_K^{-1} E_K and
+ * c_K = L_K^{-1} F_K, so that a sweep is u_K^{k+1} = c_K + G_K x_K(u^k) (the
+ * local solve of eq. iHDGlocal with the weighted trace of eq. iHDGtrace as its
+ * input x_K).  The initial iterate is u^0 = 0.  `workspace` and `scratch` are
+ * caller-owned device buffers of at least the ihdg_footprint sizes, 256-byte
+ * aligned; the workspace must outlive the context, the scratch may be freed
+ * once this returns.  *out is a library-owned host object, freed by
+ * ihdg_destroy.  `stream` is a hipStream_t.  Synchronises the stream (it
+ * checks for setup errors).  Errors (no context is returned):
+ *   IHDG_ERR_ARG          NULL or misaligned pointers, an invalid mesh, order,
+ *                         option or coefficient (e.g. kappa <= 0, Phi <= 0);
+ *   IHDG_ERR_UNSUPPORTED  a valid request this library does not serve: an
+ *                         interior transport face on which beta.n changes sign,
+ *                         a launch shape that does not apply, BiCGStab with the
+ *                         mixed precision, time stepping without a shared
+ *                         operator;
+ *   IHDG_ERR_NOMEM        workspace or scratch smaller than the footprint;
+ *   IHDG_ERR_SINGULAR_LOCAL  a local matrix with a pivot of magnitude
+ *                         <= 1e-300 or not finite (e.g. non-finite coefficients);
+ *   IHDG_ERR_HIP          a HIP call or kernel failed.
  */
 ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
                        const ihdg_options* opts, void* workspace, size_t workspace_bytes,
@@ -254,6 +266,11 @@ ihdg_status ihdg_sweep(ihdg_ctx* ctx, int32_t n_sweeps, double* incr_norm);
  * the number of sweeps (FP64 + FP32 for mixed), final_incr the last relative
  * increment, final_defect the relative FP64 defect of the returned iterate
  * (one extra FP64 sweep, not counted in iters).  Any output may be NULL.
+ * Errors: IHDG_ERR_ARG (NULL ctx, tol <= 0); IHDG_ERR_DIVERGED (a non-finite
+ * increment or residual, or an increment 1e3x above its smallest);
+ * IHDG_ERR_MAXITER (max_iters reached; for BiCGStab also four restarts in a
+ * row without progress); IHDG_ERR_HIP.  After DIVERGED or MAXITER the last
+ * iterate stays readable and final_defect is still filled in.
  */
 ihdg_status ihdg_solve(ihdg_ctx* ctx, double tol, int32_t* iters, double* final_incr,
                        double* final_defect);
