@@ -270,7 +270,8 @@ ihdg_status ihdg_sweep(ihdg_ctx* ctx, int32_t n_sweeps, double* incr_norm);
  * increment or residual, or an increment 1e3x above its smallest);
  * IHDG_ERR_MAXITER (max_iters reached; for BiCGStab also four restarts in a
  * row without progress); IHDG_ERR_HIP.  After DIVERGED or MAXITER the last
- * iterate stays readable and final_defect is still filled in.
+ * iterate stays readable; final_defect is filled in after IHDG_OK and
+ * IHDG_ERR_MAXITER only.
  */
 ihdg_status ihdg_solve(ihdg_ctx* ctx, double tol, int32_t* iters, double* final_incr,
                        double* final_defect);
