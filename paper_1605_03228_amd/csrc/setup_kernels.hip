@@ -344,12 +344,23 @@ __device__ void gauss_jordan(double* A, int n, int ncol, int* flag) {
     for (int j = k + threadIdx.x; j < ncol; j += blockDim.x) A[(int64_t)k * ncol + j] *= inv;
     for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = A[(int64_t)i * ncol + k];
     __syncthreads();
-    const double* __restrict__ rk = A + (int64_t)k * ncol;
-    for (int i = wv; i < n; i += kWaves) {
-      if (i == k) continue;
-      double* __restrict__ ri = A + (int64_t)i * ncol;
-      const double ci = colk[i];
-      for (int j = k + lane; j < ncol; j += 64) ri[j] -= ci * rk[j];
+    // each lane owns columns j, each wave rows i = wv (mod kWaves); four rows'
+    // loads are issued before their updates (row k is left as it is)
+    for (int j = k + lane; j < ncol; j += 64) {
+      const double rkj = A[(int64_t)k * ncol + j];
+      int i = wv;
+      for (; i + 3 * kWaves < n; i += 4 * kWaves) {
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = A[(int64_t)(i + q * kWaves) * ncol + j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = i + q * kWaves;
+          if (r != k) A[(int64_t)r * ncol + j] = v[q] - colk[r] * rkj;
+        }
+      }
+      for (; i < n; i += kWaves)
+        if (i != k) A[(int64_t)i * ncol + j] = A[(int64_t)i * ncol + j] - colk[i] * rkj;
     }
     __syncthreads();
   }
