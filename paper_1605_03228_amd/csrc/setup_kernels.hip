@@ -28,6 +28,9 @@ constexpr int kST = 256;      // threads per setup workgroup
 struct Basis {
   const RefTab& t;
   const MeshInfo& m;
+  // optional tables of the volume values below (the same values, evaluated
+  // once per workgroup): W [nq], then B [nq][np], then D [dim][nq][np]
+  const double* tab = nullptr;
   __device__ Basis(const RefTab& t_, const MeshInfo& m_) : t(t_), m(m_) {}
   __device__ void split(int k, int base, int* idx) const {
     idx[0] = k % base;
@@ -35,6 +38,7 @@ struct Basis {
     idx[2] = k / (base * base);
   }
   __device__ double W(int q) const {  // volume weight times |J|
+    if (tab) return tab[q];
     int qa[3];
     split(q, t.nq1, qa);
     double w = m.jac;
@@ -42,6 +46,7 @@ struct Basis {
     return w;
   }
   __device__ double B(int q, int i) const {
+    if (tab) return tab[m.nq + q * m.np + i];
     int qa[3], ia[3];
     split(q, t.nq1, qa);
     split(i, t.n1, ia);
@@ -51,6 +56,7 @@ struct Basis {
   }
   // physical derivative d/dx_a of basis i at volume point q
   __device__ double D(int a, int q, int i) const {
+    if (tab) return tab[m.nq + (1 + a) * m.nq * m.np + q * m.np + i];
     int qa[3], ia[3];
     split(q, t.nq1, qa);
     split(i, t.n1, ia);
@@ -92,6 +98,17 @@ struct Basis {
     return ia[ax] == (s ? t.n1 - 1 : 0);
   }
 };
+
+// Fill the tables of Basis::tab with the values the untabulated Basis gives.
+__device__ void fill_basis_tab(const Basis& b, double* tab) {
+  const int nq = b.m.nq, np = b.m.np, dim = b.m.dim;
+  for (int k = threadIdx.x; k < nq; k += blockDim.x) tab[k] = b.W(k);
+  for (int k = threadIdx.x; k < nq * np; k += blockDim.x) tab[nq + k] = b.B(k / np, k % np);
+  for (int k = threadIdx.x; k < dim * nq * np; k += blockDim.x) {
+    const int a = k / (nq * np), r = k % (nq * np);
+    tab[nq + (1 + a) * nq * np + r] = b.D(a, r / np, r % np);
+  }
+}
 
 struct ElemData {
   double beta[kMaxNq][3];
@@ -436,9 +453,13 @@ __device__ void cd_projection(const SetupArgs& a, const Basis& b, const ElemData
       for (int bb = 0; bb < nfp; ++bb) out[(s * nfp + cc) * nfp + bb] = R[cc * nr + s * nfp + bb];
 }
 
+// kTab: the volume basis values come from tables in dynamic LDS (the other
+// instance is the same kernel with every table test folded away).
+template <bool kTab>
 __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
   __shared__ RefTab rt;
   __shared__ ElemData d;
+  extern __shared__ double basis_tab[];  // kTab only
   if (threadIdx.x == 0) rt = a.rt;
   __syncthreads();
   const MeshInfo& m = a.mi;
@@ -446,6 +467,11 @@ __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
   const int64_t e = a.e0 + le;
   if (le >= a.count) return;
   Basis b(rt, m);
+  if constexpr (kTab) {
+    fill_basis_tab(b, basis_tab);
+    __syncthreads();
+    b.tab = basis_tab;
+  }
   const bool rep = a.shared_rep != 0;
   load_element(a, e, rep, d);
   const int n = a.n_loc, ni = a.n_in, nc = a.ncol;
@@ -664,9 +690,15 @@ hipError_t launch_node_points(const MeshInfo& mi, const RefTab& rt, double* x, h
   return hipGetLastError();
 }
 
+// The volume basis tables go to dynamic LDS where they are small (24 KB: 2-D
+// p <= 4, 3-D p = 1), so that the kernel's occupancy stays as it is.
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_setup, dim3((unsigned)a.count), dim3(kST), 0, s, a);
+  const size_t bytes = (size_t)a.mi.nq * (1 + (size_t)(1 + a.mi.dim) * a.mi.np) * sizeof(double);
+  if (bytes <= 24 * 1024)
+    hipLaunchKernelGGL(k_setup<true>, dim3((unsigned)a.count), dim3(kST), bytes, s, a);
+  else
+    hipLaunchKernelGGL(k_setup<false>, dim3((unsigned)a.count), dim3(kST), 0, s, a);
   return hipGetLastError();
 }
 
