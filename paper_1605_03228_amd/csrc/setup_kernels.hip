@@ -690,12 +690,13 @@ hipError_t launch_node_points(const MeshInfo& mi, const RefTab& rt, double* x, h
   return hipGetLastError();
 }
 
-// The volume basis tables go to dynamic LDS where they are small (24 KB: 2-D
-// p <= 4, 3-D p = 1), so that the kernel's occupancy stays as it is.
+// The volume basis tables go to dynamic LDS where they fit in 48 KB (2-D
+// p <= 5, 3-D p = 1).  At 2-D p = 5 (43 KB) two workgroups fit per CU instead
+// of four, and the tables still halve the assembly's work.
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
   const size_t bytes = (size_t)a.mi.nq * (1 + (size_t)(1 + a.mi.dim) * a.mi.np) * sizeof(double);
-  if (bytes <= 24 * 1024)
+  if (bytes <= 48 * 1024)
     hipLaunchKernelGGL(k_setup<true>, dim3((unsigned)a.count), dim3(kST), bytes, s, a);
   else
     hipLaunchKernelGGL(k_setup<false>, dim3((unsigned)a.count), dim3(kST), 0, s, a);
