@@ -309,8 +309,8 @@ __device__ double entry_F(const SetupArgs& a, const Basis& b, const ElemData& d,
 // memory; afterwards columns n..ncol-1 hold L^{-1} times the right-hand sides.
 // The pivot of column k is the first row i >= k of largest |A(i, k)| (rows
 // whose entry is NaN are never chosen; row k is kept if its own entry is NaN),
-// found by the first wave; the elimination updates one row per wave, 64
-// columns at a time.
+// found by the first wave.  In the elimination each lane owns columns and each
+// wave a quarter of the rows.
 __device__ void gauss_jordan(double* A, int n, int ncol, int* flag) {
   __shared__ double colk[kMaxNloc];
   __shared__ int piv;
