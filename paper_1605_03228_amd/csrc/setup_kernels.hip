@@ -29,8 +29,10 @@ struct Basis {
   const RefTab& t;
   const MeshInfo& m;
   // optional tables of the volume values below (the same values, evaluated
-  // once per workgroup): W [nq], then B [nq][np], then D [dim][nq][np]
+  // once per workgroup): W [nq], then B [nq][np] at tab, and D [dim][nq][np]
+  // at tabd (which may stay null while tab is set)
   const double* tab = nullptr;
+  const double* tabd = nullptr;
   __device__ Basis(const RefTab& t_, const MeshInfo& m_) : t(t_), m(m_) {}
   __device__ void split(int k, int base, int* idx) const {
     idx[0] = k % base;
@@ -56,7 +58,7 @@ struct Basis {
   }
   // physical derivative d/dx_a of basis i at volume point q
   __device__ double D(int a, int q, int i) const {
-    if (tab) return tab[m.nq + (1 + a) * m.nq * m.np + q * m.np + i];
+    if (tabd) return tabd[(a * m.nq + q) * m.np + i];
     int qa[3], ia[3];
     split(q, t.nq1, qa);
     split(i, t.n1, ia);
@@ -99,11 +101,13 @@ struct Basis {
   }
 };
 
-// Fill the tables of Basis::tab with the values the untabulated Basis gives.
-__device__ void fill_basis_tab(const Basis& b, double* tab) {
+// Fill the tables of Basis::tab (W, B) and, if with_d, of Basis::tabd (D, right
+// after them) with the values the untabulated Basis gives.
+__device__ void fill_basis_tab(const Basis& b, double* tab, bool with_d) {
   const int nq = b.m.nq, np = b.m.np, dim = b.m.dim;
   for (int k = threadIdx.x; k < nq; k += blockDim.x) tab[k] = b.W(k);
   for (int k = threadIdx.x; k < nq * np; k += blockDim.x) tab[nq + k] = b.B(k / np, k % np);
+  if (!with_d) return;
   for (int k = threadIdx.x; k < dim * nq * np; k += blockDim.x) {
     const int a = k / (nq * np), r = k % (nq * np);
     tab[nq + (1 + a) * nq * np + r] = b.D(a, r / np, r % np);
@@ -453,9 +457,9 @@ __device__ void cd_projection(const SetupArgs& a, const Basis& b, const ElemData
       for (int bb = 0; bb < nfp; ++bb) out[(s * nfp + cc) * nfp + bb] = R[cc * nr + s * nfp + bb];
 }
 
-// kTab: the volume basis values come from tables in dynamic LDS (the other
-// instance is the same kernel with every table test folded away).
-template <bool kTab>
+// kTab: 2 = W, B and D come from tables in dynamic LDS, 1 = W and B only, 0 =
+// none (in that instance every table test folds away).
+template <int kTab>
 __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
   __shared__ RefTab rt;
   __shared__ ElemData d;
@@ -467,10 +471,11 @@ __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
   const int64_t e = a.e0 + le;
   if (le >= a.count) return;
   Basis b(rt, m);
-  if constexpr (kTab) {
-    fill_basis_tab(b, basis_tab);
+  if constexpr (kTab > 0) {
+    fill_basis_tab(b, basis_tab, kTab == 2);
     __syncthreads();
     b.tab = basis_tab;
+    if constexpr (kTab == 2) b.tabd = basis_tab + m.nq + m.nq * m.np;
   }
   const bool rep = a.shared_rep != 0;
   load_element(a, e, rep, d);
@@ -690,16 +695,21 @@ hipError_t launch_node_points(const MeshInfo& mi, const RefTab& rt, double* x, h
   return hipGetLastError();
 }
 
-// The volume basis tables go to dynamic LDS where they fit in 48 KB (2-D
-// p <= 5, 3-D p = 1).  At 2-D p = 5 (43 KB) two workgroups fit per CU instead
-// of four, and the tables still halve the assembly's work.
+// The volume basis tables go to dynamic LDS where they fit in 48 KB: all of
+// them for 2-D p <= 5 and 3-D p = 1 (at 2-D p = 5, 43 KB, two workgroups fit
+// per CU instead of four, and the tables still halve the assembly's work),
+// the values without the derivatives for 2-D p = 6 and 3-D p = 2.
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
-  const size_t bytes = (size_t)a.mi.nq * (1 + (size_t)(1 + a.mi.dim) * a.mi.np) * sizeof(double);
-  if (bytes <= 48 * 1024)
-    hipLaunchKernelGGL(k_setup<true>, dim3((unsigned)a.count), dim3(kST), bytes, s, a);
+  const size_t nq = (size_t)a.mi.nq, np = (size_t)a.mi.np;
+  const size_t full = nq * (1 + (size_t)(1 + a.mi.dim) * np) * sizeof(double);
+  const size_t wb = nq * (1 + np) * sizeof(double);
+  if (full <= 48 * 1024)
+    hipLaunchKernelGGL(k_setup<2>, dim3((unsigned)a.count), dim3(kST), full, s, a);
+  else if (wb <= 48 * 1024)
+    hipLaunchKernelGGL(k_setup<1>, dim3((unsigned)a.count), dim3(kST), wb, s, a);
   else
-    hipLaunchKernelGGL(k_setup<false>, dim3((unsigned)a.count), dim3(kST), 0, s, a);
+    hipLaunchKernelGGL(k_setup<0>, dim3((unsigned)a.count), dim3(kST), 0, s, a);
   return hipGetLastError();
 }
 
