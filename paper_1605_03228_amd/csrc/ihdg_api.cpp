@@ -15,6 +15,23 @@
 
 using namespace ihdg;
 
+// Host memory that asynchronous copies read from or write into.  It belongs to
+// the context (or batch), never to a stack frame or a local container, so a
+// copy still queued when a call returns early on an error cannot touch freed
+// memory.  `pending` is set while such a copy may still be queued on the
+// stream; every call that reuses the block, and destroy, first synchronises
+// the stream.  If that synchronisation fails at destroy, the block is
+// deliberately leaked rather than freed under a copy that may still run.
+struct HostStage {
+  std::vector<double> w;    // norm weights (setup)
+  int flags[2];             // setup: singular local matrix, mixed-sign face
+  double norms[2];          // a sweep's reduced norms
+  double scal[16];          // Krylov scalars
+  std::vector<double> H;    // GMRES Hessenberg columns ((m+1) x m)
+  std::vector<double> ny;   // GMRES update coefficients (m)
+  bool pending = false;
+};
+
 struct ihdg_ctx {
   MeshInfo mi;
   RefTab rt;
@@ -55,7 +72,26 @@ struct ihdg_ctx {
   int g64_n, g32_n;
   std::string err;
   ihdg_stats stats;
+  HostStage* hs;
 };
+
+// Queue a copy between device memory and the context's host staging block.
+static hipError_t stage_copy(ihdg_ctx* c, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, c->stream);
+  if (e == hipSuccess) c->hs->pending = true;
+  return e;
+}
+
+// Wait for the context's stream; the staging block is free again on success.
+static hipError_t stage_sync(ihdg_ctx* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) c->hs->pending = false;
+  return e;
+}
+
+// Before the staging block is reused: no copy of an earlier, failed call may
+// still be queued.
+static hipError_t stage_ready(ihdg_ctx* c) { return c->hs->pending ? stage_sync(c) : hipSuccess; }
 
 static ihdg_status fail(ihdg_ctx* c, ihdg_status s, const std::string& m) {
   if (c) c->err = m;
@@ -359,6 +395,11 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   int64_t chunk = shared ? 1 : std::min<int64_t>(mi.n_el, (int64_t)(scratch_bytes / per));
 
   ihdg_ctx* c = new ihdg_ctx();
+  c->hs = new HostStage();
+  if (o.krylov_restart > 0) {
+    c->hs->H.assign((size_t)(o.krylov_restart + 1) * o.krylov_restart, 0.0);
+    c->hs->ny.assign((size_t)o.krylov_restart, 0.0);
+  }
   c->mi = mi;
   c->rt = make_reftab(order, mi.dim);
   c->pde = pde;
@@ -409,7 +450,8 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   };
   if (hipMemsetAsync(workspace, 0, L.total, st) != hipSuccess) return bail(IHDG_ERR_HIP, "memset");
   // norm weights |J| W_i per local unknown
-  std::vector<double> w(sz.n_loc);
+  std::vector<double>& w = c->hs->w;
+  w.assign(sz.n_loc, 0.0);
   for (int r = 0; r < sz.n_loc; ++r) {
     int i = r % mi.np;
     double v = mi.jac;
@@ -419,7 +461,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
     }
     w[r] = v;
   }
-  if (hipMemcpyAsync(c->wnorm, w.data(), w.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess)
+  if (stage_copy(c, c->wnorm, w.data(), w.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
     return bail(IHDG_ERR_HIP, "copy weights");
 
   SetupArgs a{};
@@ -486,9 +528,10 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
         hipMemcpyAsync(c->cf, c->c64, c->nvec * 8, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return bail(IHDG_ERR_HIP, "time operator");
   }
-  int hflags[2] = {0, 0};
-  if (hipMemcpyAsync(hflags, flags, sizeof(hflags), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess) {
+  int* hflags = c->hs->flags;
+  hflags[0] = hflags[1] = 0;
+  if (stage_copy(c, hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+      stage_sync(c) != hipSuccess) {
     ihdg_destroy(c);
     return IHDG_ERR_HIP;
   }
@@ -517,6 +560,9 @@ void ihdg_destroy(ihdg_ctx* c) {
     if (c->g64[k]) (void)hipGraphExecDestroy(c->g64[k]);
     if (c->g32[k]) (void)hipGraphExecDestroy(c->g32[k]);
   }
+  // a copy of a failed call may still be queued: free the staging block only
+  // once the stream has drained (otherwise leak it)
+  if (stage_ready(c) == hipSuccess) delete c->hs;
   delete c;
 }
 
@@ -691,6 +737,8 @@ static hipError_t run_batch(ihdg_ctx* c, bool fp32, int n) {
     if (e != hipSuccess) return e;
     e = fp32 ? batch32_enqueue(c, n) : batch64_enqueue(c, n);
     hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+    // a graph is ours to destroy only when the capture ended successfully
+    if (e != hipSuccess && e2 == hipSuccess && g) (void)hipGraphDestroy(g);
     if (e == hipErrorStreamCaptureInvalidated || e2 == hipErrorStreamCaptureInvalidated) {
       (void)hipGetLastError();
       parity = p0;  // nothing of the capture ran
@@ -713,9 +761,15 @@ static hipError_t run_batch(ihdg_ctx* c, bool fp32, int n) {
 }
 
 static hipError_t read_norms(ihdg_ctx* c, double* h2) {
-  hipError_t e = hipMemcpyAsync(h2, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = stage_ready(c);
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(c->stream);
+  e = stage_copy(c, c->hs->norms, c->norms, 2 * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  e = stage_sync(c);
+  if (e != hipSuccess) return e;
+  h2[0] = c->hs->norms[0];
+  h2[1] = c->hs->norms[1];
+  return hipSuccess;
 }
 
 // FP64 defect of the current iterate: tmp = psi(u); returns ||tmp - u||_h, ||tmp||_h
@@ -925,7 +979,11 @@ static ihdg_status solve_gmres_t(ihdg_ctx* c, double tol, int32_t* iters, double
   double* hcur = Hc + (size_t)m1 * m;                      // this pass's coefficients
   double* scal = hcur + m1;                                // [0]: squared norm
   double* ydev = scal + 8;                                 // update coefficients
-  std::vector<double> H((size_t)m1 * m), cs(m), sn(m), g(m1), y(m), ny(m);
+  // Hessenberg columns and update coefficients live in the context's staging
+  // block (copies into and out of them are asynchronous)
+  std::vector<double>& H = c->hs->H;
+  std::vector<double>& ny = c->hs->ny;
+  std::vector<double> cs(m), sn(m), g(m1), y(m);
   int64_t it = 0;
   double rel = INFINITY;
   double* u = c->u64[c->cur];
@@ -933,9 +991,11 @@ static ihdg_status solve_gmres_t(ihdg_ctx* c, double tol, int32_t* iters, double
   auto norm2 = [&](const auto* x, double* out) -> hipError_t {
     hipError_t e = launch_kdots(x, x, N, 1, c->wnorm, n_loc, part, scal, nullptr, 0, st);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    e = stage_copy(c, c->hs->scal, scal, sizeof(double), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return e;
-    return hipStreamSynchronize(st);
+    e = stage_sync(c);
+    if (e == hipSuccess) *out = c->hs->scal[0];
+    return e;
   };
   // A v = v - psi(v) + c (FP64), or v - T v with the FP32 operators and a zero
   // affine part (d32 holds zeros during the solve), written into out
@@ -965,6 +1025,7 @@ static ihdg_status solve_gmres_t(ihdg_ctx* c, double tol, int32_t* iters, double
     if (e == hipSuccess) e = launch_knormalize(w, N, scal, hcol + j + 1, st);
     return e;
   };
+  HIPCHK(c, stage_ready(c));
   double bnorm;
   {
     double d;
@@ -1012,9 +1073,9 @@ static ihdg_status solve_gmres_t(ihdg_ctx* c, double tol, int32_t* iters, double
     for (int j0 = 0; j0 < m && !conv && it < c->opt.max_iters;) {
       const int j1 = (int)std::min<int64_t>({(int64_t)m, (int64_t)j0 + kCheck, (int64_t)j0 + (c->opt.max_iters - it)});
       for (int j = j0; j < j1; ++j) HIPCHK(c, arnoldi(j));
-      HIPCHK(c, hipMemcpyAsync(H.data() + (size_t)j0 * m1, Hc + (size_t)j0 * m1, (size_t)(j1 - j0) * m1 * 8,
-                               hipMemcpyDeviceToHost, st));
-      HIPCHK(c, hipStreamSynchronize(st));
+      HIPCHK(c, stage_copy(c, H.data() + (size_t)j0 * m1, Hc + (size_t)j0 * m1, (size_t)(j1 - j0) * m1 * 8,
+                           hipMemcpyDeviceToHost));
+      HIPCHK(c, stage_sync(c));
       for (int j = j0; j < j1; ++j) {
         double* h = H.data() + (size_t)j * m1;  // column j: h[i] = H(i, j)
         for (int i = 0; i < j; ++i) {
@@ -1050,9 +1111,9 @@ static ihdg_status solve_gmres_t(ihdg_ctx* c, double tol, int32_t* iters, double
     }
     if (used > 0) {
       for (int i = 0; i < used; ++i) ny[i] = -y[i];  // the fused update subtracts
-      HIPCHK(c, hipMemcpyAsync(ydev, ny.data(), used * 8, hipMemcpyHostToDevice, st));
+      HIPCHK(c, stage_copy(c, ydev, ny.data(), used * 8, hipMemcpyHostToDevice));
       HIPCHK(c, launch_multi_axpy(u, V, ydev, used, N, st));
-      HIPCHK(c, hipStreamSynchronize(st));  // y is host memory the next copy may reuse
+      HIPCHK(c, stage_sync(c));  // ny is reused by the next cycle
     }
     if (iters) *iters = (int32_t)it;
   }
@@ -1089,11 +1150,12 @@ static ihdg_status solve_bicgstab(ihdg_ctx* c, double tol, int32_t* iters, doubl
   double* partB = part + (size_t)ihdg::kDotGroups * 2;  // partials B: (t, s), (t, t)
   double* sc = part + (size_t)ihdg::kDotGroups * 4;     // 16 scalars
   double* u = c->u64[c->cur];
-  double hsc[16];
+  double* hsc = c->hs->scal;  // the context's staging block (asynchronous copy target)
   auto readsc = [&]() -> hipError_t {
-    hipError_t e = hipMemcpyAsync(hsc, sc, sizeof(hsc), hipMemcpyDeviceToHost, st);
-    return e == hipSuccess ? hipStreamSynchronize(st) : e;
+    hipError_t e = stage_copy(c, hsc, sc, 16 * sizeof(double), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? stage_sync(c) : e;
   };
+  HIPCHK(c, stage_ready(c));
   double bnorm;
   HIPCHK(c, launch_kdots(c->c64, c->c64, N, 1, c->wnorm, n_loc, part, sc + 7, nullptr, 0, st));
   HIPCHK(c, readsc());
@@ -1210,6 +1272,16 @@ struct ihdg_batch {
   bool use_graphs = true;
   hipGraphExec_t graph = nullptr;
   std::vector<int64_t> graph_sig;
+  // host staging of a round (descriptors, block owners, norms): asynchronous
+  // copies read from and write into it, so it lives with the batch, and a
+  // round first waits for any copy an earlier failed round left queued
+  struct Stage {
+    std::vector<BatchDesc> hd;
+    std::vector<int> ho;
+    std::vector<double> hn;
+    bool pending = false;
+  };
+  Stage* stage = new Stage();
 };
 
 static size_t batch_bytes(int32_t mm, int64_t mb, size_t* off_owner, size_t* off_norms) {
@@ -1267,6 +1339,8 @@ const char* ihdg_batch_last_error(const ihdg_batch* b) { return b ? b->err.c_str
 void ihdg_batch_destroy(ihdg_batch* b) {
   if (!b) return;
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  // free the staging only once no copy of a failed round can still run
+  if (!b->stage->pending || hipStreamSynchronize(b->stream) == hipSuccess) delete b->stage;
   delete b;
 }
 
@@ -1306,6 +1380,14 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
     if (n_active) *n_active = 0;
     return IHDG_OK;
   }
+  ihdg_batch::Stage& sg = *b->stage;
+  if (sg.pending) {
+    if (hipError_t e = hipStreamSynchronize(st); e != hipSuccess) {
+      b->err = std::string("synchronize before reusing the staging: ") + hipGetErrorName(e);
+      return IHDG_ERR_HIP;
+    }
+    sg.pending = false;
+  }
   // group members by kernel shape and mode
   typedef std::tuple<int, int, int, int, int, int, int> Key;  // pde, dim, p, shared, fp32, single, waves
   std::map<Key, std::vector<int>> groups;
@@ -1316,8 +1398,10 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
           m.mode == kModeDefect ? 1 : 0, m.mode == kModeF32 ? c->waves32 : c->waves};
     groups[k].push_back(i);
   }
-  std::vector<BatchDesc> hd;
-  std::vector<int> ho;
+  std::vector<BatchDesc>& hd = sg.hd;
+  std::vector<int>& ho = sg.ho;
+  hd.clear();
+  ho.clear();
   std::vector<int> order;  // desc slot -> active index
   struct G {
     Key k;
@@ -1378,6 +1462,7 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
   if (hipError_t e = hipMemcpyAsync(b->descs, hd.data(), hd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, st);
       e != hipSuccess)
     return bfail("copy descriptors", e);
+  sg.pending = true;
   if (hipError_t e = hipMemcpyAsync(b->owner, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice, st);
       e != hipSuccess)
     return bfail("copy block owners", e);
@@ -1419,6 +1504,8 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
         return bfail("begin capture", e0);
       const hipError_t e = enqueue();
       const hipError_t e2 = hipStreamEndCapture(st, &g);
+      // a graph is ours to destroy only when the capture ended successfully
+      if (e != hipSuccess && e2 == hipSuccess && g) (void)hipGraphDestroy(g);
       if (e == hipErrorStreamCaptureInvalidated || e2 == hipErrorStreamCaptureInvalidated) {
         (void)hipGetLastError();  // the failed launch's error, not a device fault
         if (hipError_t e4 = enqueue(); e4 != hipSuccess) return bfail("launch after an invalidated capture", e4);
@@ -1440,11 +1527,13 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
   } else if (hipError_t e = enqueue(); e != hipSuccess) {
     return bfail("launch", e);
   }
-  std::vector<double> hn(2 * hd.size());
+  std::vector<double>& hn = sg.hn;
+  hn.assign(2 * hd.size(), 0.0);
   if (hipError_t e = hipMemcpyAsync(hn.data(), b->norms, hn.size() * sizeof(double), hipMemcpyDeviceToHost, st);
       e != hipSuccess)
     return bfail("copy norms", e);
   if (hipError_t e = hipStreamSynchronize(st); e != hipSuccess) return bfail("synchronize", e);
+  sg.pending = false;
   // state machines
   std::vector<char> finished(b->active.size(), 0);
   for (size_t slot = 0; slot < order.size(); ++slot) {
