@@ -379,6 +379,9 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
     case 3:
       if (!shared) return IHDG_ERR_UNSUPPORTED;
       break;
+    case 6:
+      if (!shared || pde != IHDG_TRANSPORT || !ihdg::gemm_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
+      break;
     case 5:
       if (!shared) return IHDG_ERR_UNSUPPORTED;
       if (pde == IHDG_TRANSPORT && !ihdg::direct_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
@@ -608,6 +611,7 @@ static hipError_t one_sweep(ihdg_ctx* c, bool fp32, const void* uin, void* uout,
   a.wnorm = c->wnorm;
   a.partials = c->partials;
   a.n_blk = c->mi.n_blk;
+  a.n_el = c->mi.n_el;
   a.sqrt_phi = c->sqrt_phi;
   return ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, fp32 ? c->waves32 : c->waves, a,
                             c->stream);
@@ -640,6 +644,7 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
   }
   std::vector<int> cand = c->shared ? std::vector<int>{4, 8, 3} : std::vector<int>{1, 2, 4, 8};
   if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::direct_supported(c->mi.dim, c->mi.p)) cand.push_back(5);
+  if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::gemm_supported(c->mi.dim, c->mi.p)) cand.push_back(6);
   if (c->shared && c->pde == IHDG_CONVDIFF && ihdg::direct_cd_supported(c->mi.p)) cand.push_back(5);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   struct Events {  // destroyed on every return path
@@ -671,6 +676,7 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
     a.wnorm = c->wnorm;
     a.partials = c->partials;
     a.n_blk = nb;
+    a.n_el = c->mi.n_el;
     a.sqrt_phi = c->sqrt_phi;
     for (int i = 0; i < 2; ++i)
       if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, a, c->stream)) != hipSuccess)
@@ -1443,6 +1449,7 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
       d.wnorm = c->wnorm;
       d.partials = c->partials;
       d.n_blk = c->mi.n_blk;
+      d.n_el = c->mi.n_el;
       d.blk0 = g.nb;
       d.sqrt_phi = c->sqrt_phi;
       for (int64_t k = 0; k < c->mi.n_blk; ++k) ho.push_back(local);

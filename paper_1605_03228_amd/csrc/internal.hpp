@@ -56,6 +56,7 @@ struct SweepArgs {
   const double* wnorm;  // [n_loc] |J| x GLL weight of each local unknown
   double* partials;     // [n_blk][2]: sum w (uout-uin)^2, sum w uout^2
   int64_t n_blk;
+  int64_t n_el;         // elements (the last block's lanes past it are padding)
   double sqrt_phi;      // shallow water sqrt(Phi)
 };
 
@@ -70,6 +71,7 @@ struct BatchDesc {
   const double* wnorm;
   double* partials;
   int64_t n_blk;
+  int64_t n_el;
   int64_t blk0;
   double sqrt_phi;
   int parity0;
@@ -88,6 +90,7 @@ __host__ __device__ inline SweepArgs batch_args(const BatchDesc& d, int s) {
   a.wnorm = d.wnorm;
   a.partials = d.partials;
   a.n_blk = d.n_blk;
+  a.n_el = d.n_el;
   a.sqrt_phi = d.sqrt_phi;
   return a;
 }
@@ -112,6 +115,9 @@ hipError_t launch_sweep_cd(int p, bool fp32, bool shared, int waves, const Sweep
 // True where the transport matrix-core variant without LDS staging (launch
 // shape 5, shared operators only) has an instance.
 bool direct_supported(int dim, int p);
+// True where the transport staged-GEMM variant (launch shape 6, shared
+// operators only) has an instance.
+bool gemm_supported(int dim, int p);
 // the convection-diffusion direct kernel (launch shape 5, shared operator, 2-D) fits for order p
 bool direct_cd_supported(int p);
 

@@ -1,5 +1,6 @@
 // Sweep kernel instances for transport (2-D p = 1..6, 3-D p = 1..4).
 #include "sweep_direct.hpp"
+#include "sweep_gemm.hpp"
 #include "sweep_impl.hpp"
 
 namespace ihdg {
@@ -28,6 +29,62 @@ bool direct_supported(int dim, int p) {
     }
   }
   return false;
+}
+
+template <int DIM, int P>
+static constexpr bool gemm_ok() {
+  return GemmShape<double, DIM, P>::OK && GemmShape<float, DIM, P>::OK;
+}
+
+// Instances: 3-D p <= 3 (config 3's shape and its neighbours), and 2-D p = 2
+// and 6, which exercise the padded K slices and the ragged last row tile.
+bool gemm_supported(int dim, int p) {
+  if (dim == 2) {
+    switch (p) {
+      case 2: return gemm_ok<2, 2>();
+      case 6: return gemm_ok<2, 6>();
+    }
+  } else if (dim == 3) {
+    switch (p) {
+      case 1: return gemm_ok<3, 1>();
+      case 2: return gemm_ok<3, 2>();
+      case 3: return gemm_ok<3, 3>();
+    }
+  }
+  return false;
+}
+
+static hipError_t launch_gemm_any(int dim, int p, bool fp32, const SweepArgs& a, hipStream_t s) {
+  if (dim == 2) {
+    switch (p) {
+      case 2: return launch_gemm<2, 2>(fp32, a, s);
+      case 6: return launch_gemm<2, 6>(fp32, a, s);
+    }
+  } else if (dim == 3) {
+    switch (p) {
+      case 1: return launch_gemm<3, 1>(fp32, a, s);
+      case 2: return launch_gemm<3, 2>(fp32, a, s);
+      case 3: return launch_gemm<3, 3>(fp32, a, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+static hipError_t launch_gemm_batched_any(int dim, int p, bool fp32, const BatchDesc* d, const int* owner, int64_t nb,
+                                          int sidx, hipStream_t s) {
+  if (dim == 2) {
+    switch (p) {
+      case 2: return launch_gemm_batched<2, 2>(fp32, d, owner, nb, sidx, s);
+      case 6: return launch_gemm_batched<2, 6>(fp32, d, owner, nb, sidx, s);
+    }
+  } else if (dim == 3) {
+    switch (p) {
+      case 1: return launch_gemm_batched<3, 1>(fp32, d, owner, nb, sidx, s);
+      case 2: return launch_gemm_batched<3, 2>(fp32, d, owner, nb, sidx, s);
+      case 3: return launch_gemm_batched<3, 3>(fp32, d, owner, nb, sidx, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 static hipError_t launch_direct_any(int dim, int p, bool fp32, const SweepArgs& a, hipStream_t s) {
@@ -76,6 +133,7 @@ static hipError_t launch_direct_batched_any(int dim, int p, bool fp32, const Bat
 hipError_t launch_sweep_transport(int dim, int p, bool fp32, bool shared, int waves, const SweepArgs& a,
                                   hipStream_t s) {
   if (waves == 5) return shared ? launch_direct_any(dim, p, fp32, a, s) : hipErrorNotSupported;
+  if (waves == 6) return shared ? launch_gemm_any(dim, p, fp32, a, s) : hipErrorNotSupported;
   if (dim == 2) {
     switch (p) {
       case 1: return launch_variants<kTransport, 2, 1>(fp32, shared, waves, a, s);
@@ -99,6 +157,7 @@ hipError_t launch_sweep_transport(int dim, int p, bool fp32, bool shared, int wa
 hipError_t launch_sweep_batched_transport(int dim, int p, bool fp32, bool shared, int waves, const BatchDesc* d,
                                           const int* owner, int64_t nb, int sidx, hipStream_t s) {
   if (waves == 5) return shared ? launch_direct_batched_any(dim, p, fp32, d, owner, nb, sidx, s) : hipErrorNotSupported;
+  if (waves == 6) return shared ? launch_gemm_batched_any(dim, p, fp32, d, owner, nb, sidx, s) : hipErrorNotSupported;
   if (dim == 2) {
     switch (p) {
       case 1: return launch_variants_batched<kTransport, 2, 1>(fp32, shared, waves, d, owner, nb, sidx, s);

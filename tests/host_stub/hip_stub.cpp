@@ -208,6 +208,7 @@ hipError_t launch_sweep_transport(int, int, bool, bool, int, const SweepArgs&, h
 hipError_t launch_sweep_sw(int, bool, bool, int, const SweepArgs&, hipStream_t s) { return nop(s); }
 hipError_t launch_sweep_cd(int, bool, bool, int, const SweepArgs&, hipStream_t s) { return nop(s); }
 bool direct_supported(int, int) { return true; }
+bool gemm_supported(int, int) { return true; }
 bool direct_cd_supported(int) { return true; }
 hipError_t launch_sweep_batched_transport(int, int, bool, bool, int, const BatchDesc*, const int*, int64_t, int,
                                           hipStream_t s) {

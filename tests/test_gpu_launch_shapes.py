@@ -8,7 +8,9 @@ several 64-element blocks with a ragged last block:
 * shared operators: 4 and 8 waves (matrix cores, traces staged in LDS),
   3 (vector FMA), 5 (transport and convection-diffusion: matrix cores fed
   straight from the iterate, no LDS staging; for convection-diffusion the
-  face projection is folded into the operator).
+  face projection is folded into the operator), 6 (transport: the block's
+  iterate and its inflow halo staged once in LDS, G in registers, persistent
+  with the next block's loads in flight).
 
 Bar: one sweep is an affine map applied in FP64, so after a few sweeps the
 iterates agree with the oracle's to rounding (1e-12 relative in the h-norm);
@@ -62,7 +64,7 @@ SHARED = [
     ("3d_7cube_p2", lambda: w.config3(n=7, p=2)),
     ("3d_5cube_p3", lambda: w.config3(n=5, p=3)),
 ]
-SHAPES = [(name, make, wv, {}) for name, make in SHARED for wv in (3, 4, 5, 8)]
+SHAPES = [(name, make, wv, {}) for name, make in SHARED for wv in (3, 4, 5, 6, 8)]
 SHAPES += [("cfg2_13x11_p3_per_el", _ragged_cfg2, wv, {}) for wv in (1, 2, 4, 8)]
 SHAPES += [("3d_4cube_p4_shared", lambda: w.config3(n=4, p=4), wv, {}) for wv in (3, 4, 8)]
 CD_SHARED = [
@@ -128,19 +130,44 @@ def test_bicgstab_on_every_cd_shared_shape(waves):
     s.close()
 
 
-def test_direct_variant_batched_equals_single_bitwise():
+@pytest.mark.parametrize("name,make", [SHARED[i] for i in (0, 1, 2, 3, 4)], ids=[SHARED[i][0] for i in range(5)])
+def test_staged_gemm_equals_direct_bitwise(name, make):
+    """The staged-GEMM kernel (6) runs the direct kernel's (5) MFMA sequence on
+    the same operands (same K order, same tiles), so every FP64 iterate is the
+    same bit for bit; the FP32 correction sweeps of a mixed solve as well."""
+    pr = make()
+    a, b = _solver(pr, block_waves=5), _solver(pr, block_waves=6)
+    for k in (1, 2, 3):
+        a.sweep(k)
+        b.sweep(k)
+        assert np.array_equal(_u(a), _u(b)), k
+    a.close()
+    b.close()
+    a, b = _solver(pr, block_waves=5, prec=1), _solver(pr, block_waves=6, prec=1)
+    ra, rb = a.solve(1e-10), b.solve(1e-10)
+    assert ra["status"] == rb["status"] == 0
+    assert (ra["fp32_sweeps"], ra["fp64_sweeps"]) == (rb["fp32_sweeps"], rb["fp64_sweeps"])
+    assert np.array_equal(_u(a), _u(b))
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("waves", [5, 6])
+def test_direct_variant_batched_equals_single_bitwise(waves):
     from paper_1605_03228_amd import Batch
     items = [w.config3(n=5, p=3), w.transport_const((19, 13), 2, (1.0, 0.5)), w.config3(seed=2, n=6, p=3),
              w.cd_poly((17, 9), 2, kappa=0.3, affine_beta=False), w.cd_elliptic((5, 7), 3, gamma=1.0, nu=1.0)]
+    if waves == 6:  # the staged-GEMM kernel is transport-only
+        items = items[:3] + [w.config3(seed=3, n=7, p=2), w.config3(seed=4, n=9, p=1)]
     singles = []
     for pr in items:
-        s = _solver(pr, block_waves=5)
+        s = _solver(pr, block_waves=waves)
         res = s.solve(1e-11)
         singles.append((res["iters"], _u(s)))
         s.close()
     b = Batch(max_members=8)
     for i, pr in enumerate(items):
-        b.add(_solver(pr, block_waves=5), 1e-11, i)
+        b.add(_solver(pr, block_waves=waves), 1e-11, i)
     got = {}
     for _ in range(100000):
         n = b.round(16)
@@ -163,7 +190,10 @@ def test_launch_shape_validation():
              (w.cd_smooth((6, 5), 3, kappa=1e-2), 5, 2),          # per-element operators
              (_ragged_cfg2(), 3, 2),                              # vector-FMA shared variant, per-element operators
              (_ragged_cfg2(), 5, 2),
-             (w.config1(), 6, 1), (w.config1(), -1, 1)]           # not a launch shape
+             (w.cd_elliptic((4, 4), 3, gamma=1.0), 6, 2),         # staged GEMM: transport only
+             (w.config3(n=3, p=4), 6, 2),                         # staged GEMM: no 3-D p = 4 instance
+             (_ragged_cfg2(), 6, 2),                              # staged GEMM: shared operators only
+             (w.config1(), 7, 1), (w.config1(), -1, 1)]           # not a launch shape
     for pr, wv, status in cases:
         with pytest.raises(IhdgError) as e:
             _solver(pr, block_waves=wv)
