@@ -250,6 +250,25 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
                        void* scratch, size_t scratch_bytes, void* stream, ihdg_ctx** out);
 
 /*
+ * ihdg_setup for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same setup and the same context, without the `scratch` argument.  The setup
+ * scratch is a 64 MiB device array inside the library (one per device, held
+ * until the process ends); local problems are assembled and reduced in chunks
+ * that fit it.  Calls no hipMalloc, hipFree or other allocating routine and
+ * creates no HIP events: with opts.block_waves = 0 the launch shape is the one
+ * the autotuner has cached for this problem shape, else 4 waves per block
+ * (nothing is timed).  Calls in one process are serialised (the array is
+ * shared) and each has finished its device work when it returns.  The caller
+ * still provides the workspace (the footprint's persistent_bytes).  Errors as
+ * ihdg_setup, and IHDG_ERR_NOMEM if one element's local problem does not fit
+ * the 64 MiB (no supported order comes near it).
+ */
+ihdg_status ihdg_setup_noalloc(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
+                               const ihdg_options* opts, void* workspace, size_t workspace_bytes, void* stream,
+                               ihdg_ctx** out);
+
+/*
  * Run n_sweeps iHDG sweeps (Algorithm 1, the local solve and trace update) in
  * the context's working precision: FP64 for IHDG_FP64; for IHDG_MIXED the
  * sweeps are FP64 too (ihdg_solve is where the mixed path runs).  If

@@ -68,7 +68,7 @@ EXPORTS = ["ihdg_sizes", "ihdg_quadrature_points", "ihdg_footprint", "ihdg_setup
            "ihdg_get_stats", "ihdg_last_error", "ihdg_status_string", "ihdg_destroy",
            "ihdg_batch_footprint", "ihdg_batch_create", "ihdg_batch_add", "ihdg_batch_round",
            "ihdg_batch_poll", "ihdg_batch_use_graphs", "ihdg_batch_destroy", "ihdg_batch_last_error",
-           "ihdg_time_step", "ihdg_node_points"]
+           "ihdg_time_step", "ihdg_node_points", "ihdg_setup_noalloc"]
 
 
 def load():
@@ -87,6 +87,8 @@ def load():
                                    P(C.c_size_t)]
     lib.ihdg_setup.argtypes = [P(Mesh), C.c_int32, C.c_int, P(Coeffs), P(Options), C.c_void_p, C.c_size_t,
                                C.c_void_p, C.c_size_t, C.c_void_p, P(C.c_void_p)]
+    lib.ihdg_setup_noalloc.argtypes = [P(Mesh), C.c_int32, C.c_int, P(Coeffs), P(Options), C.c_void_p, C.c_size_t,
+                                       C.c_void_p, P(C.c_void_p)]
     lib.ihdg_sweep.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
     lib.ihdg_solve.argtypes = [C.c_void_p, C.c_double, P(C.c_int32), P(C.c_double), P(C.c_double)]
     lib.ihdg_residual.argtypes = [C.c_void_p, P(C.c_double)]
@@ -217,7 +219,9 @@ def footprint(n, order, pde, coeffs=None, lo=None, hi=None, **opts):
 class Solver:
     """One iHDG problem resident on the GPU (owns its torch-allocated workspace)."""
 
-    def __init__(self, n, order, pde, coeffs, lo=None, hi=None, device="cuda", **opts):
+    def __init__(self, n, order, pde, coeffs, lo=None, hi=None, device="cuda", noalloc=False, **opts):
+        """noalloc: set up through ihdg_setup_noalloc (the library's own device
+        scratch; only the workspace is allocated here)."""
         lib = load()
         self.lib, self.device = lib, torch.device(device)
         self.n, self.order, self.pde = tuple(n), order, pde
@@ -229,16 +233,21 @@ class Solver:
         _check(lib.ihdg_footprint(C.byref(mesh), order, pde, C.byref(cf), C.byref(op), C.byref(pb), C.byref(sb)))
         self.workspace_bytes, self.scratch_bytes = pb.value, sb.value
         self.workspace = torch.empty(pb.value, dtype=torch.uint8, device=self.device)
-        scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
         # the library works on a stream of its own (default priority); torch's
         # current stream has produced the coefficient arrays, so wait for it
         self.stream = torch.cuda.Stream(device=self.device)
         torch.cuda.current_stream(self.device).synchronize()
         ctx = C.c_void_p()
-        st = lib.ihdg_setup(C.byref(mesh), order, pde, C.byref(cf), C.byref(op),
-                            C.c_void_p(self.workspace.data_ptr()), pb.value, C.c_void_p(scratch.data_ptr()),
-                            sb.value, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
-        del scratch
+        if noalloc:
+            st = lib.ihdg_setup_noalloc(C.byref(mesh), order, pde, C.byref(cf), C.byref(op),
+                                        C.c_void_p(self.workspace.data_ptr()), pb.value,
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        else:
+            scratch = torch.empty(sb.value, dtype=torch.uint8, device=self.device)
+            st = lib.ihdg_setup(C.byref(mesh), order, pde, C.byref(cf), C.byref(op),
+                                C.c_void_p(self.workspace.data_ptr()), pb.value, C.c_void_p(scratch.data_ptr()),
+                                sb.value, C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+            del scratch
         _check(st)
         self.ctx = ctx
 

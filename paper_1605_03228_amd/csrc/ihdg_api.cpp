@@ -9,6 +9,7 @@
 #include <cstring>
 #include <string>
 #include <type_traits>
+#include <mutex>
 #include <vector>
 
 #include "internal.hpp"
@@ -271,7 +272,7 @@ static Layout make_layout(const MeshInfo& m, const ihdg_sizes_t& sz, bool shared
   return L;
 }
 
-static hipError_t autotune(ihdg_ctx* c);
+static hipError_t autotune(ihdg_ctx* c, bool timed);
 static hipError_t one_sweep(ihdg_ctx* c, bool fp32, const void* uin, void* uout, const void* cvec);
 
 // ---------------------------------------------------------------------------
@@ -348,9 +349,13 @@ ihdg_status ihdg_footprint(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, c
   return IHDG_OK;
 }
 
-ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
-                       const ihdg_options* opts, void* workspace, size_t workspace_bytes, void* scratch,
-                       size_t scratch_bytes, void* stream, ihdg_ctx** out) {
+}  // extern "C"
+
+// ihdg_setup with the setup scratch given; `timed` = 0 skips the autotuner's
+// timing (cached or default launch shape, no events created).
+static ihdg_status setup_impl(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
+                              const ihdg_options* opts, void* workspace, size_t workspace_bytes, void* scratch,
+                              size_t scratch_bytes, void* stream, ihdg_ctx** out, bool timed) {
   if (!out || !coeffs || !workspace || !scratch) return IHDG_ERR_ARG;
   std::string why;
   MeshInfo mi;
@@ -547,7 +552,7 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
     return IHDG_ERR_SINGULAR_LOCAL;
   }
   if (o.block_waves == 0) {
-    if (autotune(c) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+    if (autotune(c, timed) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
       ihdg_destroy(c);
       return IHDG_ERR_HIP;
     }
@@ -555,6 +560,38 @@ ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const
   c->stats.kernel_waves = c->waves;
   *out = c;
   return IHDG_OK;
+}
+
+extern "C" {
+
+ihdg_status ihdg_setup(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
+                       const ihdg_options* opts, void* workspace, size_t workspace_bytes, void* scratch,
+                       size_t scratch_bytes, void* stream, ihdg_ctx** out) {
+  return setup_impl(mesh, order, pde, coeffs, opts, workspace, workspace_bytes, scratch, scratch_bytes, stream, out,
+                    true);
+}
+
+ihdg_status ihdg_setup_noalloc(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde, const ihdg_coeffs* coeffs,
+                               const ihdg_options* opts, void* workspace, size_t workspace_bytes, void* stream,
+                               ihdg_ctx** out) {
+  if (!out || !coeffs || !workspace) return IHDG_ERR_ARG;
+  // the one local problem that must fit the device scratch at once
+  MeshInfo mi;
+  ihdg_sizes_t sz{};
+  std::string why;
+  ihdg_status s = make_sizes(mesh, order, pde, &mi, &sz, &why);
+  if (s != IHDG_OK) return s;
+  size_t per_shared = (size_t)sz.n_loc * (2 * sz.n_loc + sz.n_in) * 8;
+  size_t per_elem = (size_t)sz.n_loc * (sz.n_loc + sz.n_in + 1) * 8;
+  if (std::max(per_shared, per_elem) > ihdg::kNoAllocScratchBytes) return IHDG_ERR_NOMEM;
+  void* scratch = nullptr;
+  if (ihdg::noalloc_scratch((hipStream_t)stream, &scratch) != hipSuccess) return IHDG_ERR_HIP;
+  // calls share the device's scratch: one at a time (each has finished its
+  // device work when it returns, since setup synchronises its stream)
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  return setup_impl(mesh, order, pde, coeffs, opts, workspace, workspace_bytes, scratch, ihdg::kNoAllocScratchBytes,
+                    stream, out, false);
 }
 
 void ihdg_destroy(ihdg_ctx* c) {
@@ -629,7 +666,9 @@ static hipError_t one_sweep(ihdg_ctx* c, bool fp32, const void* uin, void* uout,
 static std::mutex g_tune_mu;
 static std::map<std::tuple<int, int, int, int, int, int>, int> g_tuned;
 
-static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
+// timed = false: the cached choice, else the default shape (4 waves), without
+// timing anything (no events are created).
+static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best, bool timed) {
   const int64_t nb = c->mi.n_blk;
   int cls = 0;
   while ((int64_t)1 << (cls + 1) <= nb) ++cls;
@@ -641,6 +680,10 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
       *best = it->second;
       return hipSuccess;
     }
+  }
+  if (!timed) {
+    *best = 4;
+    return hipSuccess;
   }
   std::vector<int> cand = c->shared ? std::vector<int>{4, 8, 3} : std::vector<int>{1, 2, 4, 8};
   if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::direct_supported(c->mi.dim, c->mi.p)) cand.push_back(5);
@@ -700,10 +743,10 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best) {
   return hipSuccess;
 }
 
-static hipError_t autotune(ihdg_ctx* c) {
-  hipError_t e = tune_one(c, false, &c->waves);
+static hipError_t autotune(ihdg_ctx* c, bool timed) {
+  hipError_t e = tune_one(c, false, &c->waves, timed);
   if (e != hipSuccess) return e;
-  if (c->mixed) return tune_one(c, true, &c->waves32);
+  if (c->mixed) return tune_one(c, true, &c->waves32, timed);
   c->waves32 = c->waves;
   return hipSuccess;
 }

@@ -95,6 +95,11 @@ __host__ __device__ inline SweepArgs batch_args(const BatchDesc& d, int s) {
   return a;
 }
 
+// Size of the device-resident setup scratch of ihdg_setup_noalloc, and its
+// address on the device of stream s (looked up once per device).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+hipError_t noalloc_scratch(hipStream_t s, void** out);
+
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
 hipError_t launch_shared_c(const SetupArgs& a, hipStream_t s);
 hipError_t launch_maps(const SetupArgs& a, int* fmap, hipStream_t s);

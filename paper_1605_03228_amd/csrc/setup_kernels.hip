@@ -14,6 +14,8 @@
 
 #include "internal.hpp"
 
+#include <mutex>
+
 namespace ihdg {
 
 constexpr int kMaxNq = 216;   // (p+2)^3 for p = 4
@@ -725,6 +727,45 @@ hipError_t launch_maps(const SetupArgs& a, int* fmap, hipStream_t s) {
   if (blocks > 65535u * 16u) blocks = 65535u * 16u;
   hipLaunchKernelGGL(k_maps, dim3(blocks), dim3(256), 0, s, a, fmap);
   return hipGetLastError();
+}
+
+// Setup scratch of ihdg_setup_noalloc: one copy per device, held until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returned for the device, kept per device below.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(hipStream_t s, void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  int dev = -1, cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (s) {
+    hipDevice_t d = 0;
+    if ((e = hipStreamGetDevice(s, &d)) != hipSuccess) return e;
+    dev = (int)d;
+  } else {
+    dev = cur;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!ptr[dev]) {
+    // the symbol's address on device dev, looked up with that device current
+    if (dev != cur && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (dev != cur) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_quad_points(const MeshInfo& mi, const RefTab& rt, double* xq, double* xfq, hipStream_t s) {

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -209,6 +210,12 @@ hipError_t launch_sweep_sw(int, bool, bool, int, const SweepArgs&, hipStream_t s
 hipError_t launch_sweep_cd(int, bool, bool, int, const SweepArgs&, hipStream_t s) { return nop(s); }
 bool direct_supported(int, int) { return true; }
 bool gemm_supported(int, int) { return true; }
+hipError_t noalloc_scratch(hipStream_t, void** out) {
+  static void* buf = std::malloc(kNoAllocScratchBytes);
+  if (inject()) return fail_with(hipErrorUnknown);
+  *out = buf;
+  return hipSuccess;
+}
 bool direct_cd_supported(int) { return true; }
 hipError_t launch_sweep_batched_transport(int, int, bool, bool, int, const BatchDesc*, const int*, int64_t, int,
                                           hipStream_t s) {
