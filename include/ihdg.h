@@ -187,6 +187,17 @@ typedef struct {
                               caps the iterations; prec must be IHDG_FP64 (else IHDG_ERR_UNSUPPORTED).
                               The iHDG sweep as the Krylov operator is the use the paper suggests
                               for regimes where the plain iteration fails (end of Section 4)      */
+  int32_t mixed_period;    /* IHDG_MIXED without krylov_restart: FP32 correction sweeps between
+                              two FP64 defect sweeps (0 = 4 x check_every).  Every outer step
+                              forms the FP64 defect d = psi(u) - u, starts the FP32 correction
+                              at delta = d (the first sweep from zero), runs this many FP32
+                              sweeps delta <- d + G32 x(delta) and adds delta to u in FP64, so
+                              the solve advances the iteration by mixed_period + 1 sweeps per
+                              outer step.  Once the last defect is within 1e3 x tol, a round of
+                              check_every FP32 sweeps whose increment meets tol ends the
+                              correction early (the FP64 defect then decides).  < 0: each
+                              correction runs until its increment falls below inner_rtol or
+                              stalls at the FP32 rounding floor                                */
 } ihdg_options;
 
 /* Discretisation sizes for (mesh, order, pde).  No device work. */
@@ -277,6 +288,16 @@ ihdg_status ihdg_setup_noalloc(const ihdg_mesh* mesh, int32_t order, ihdg_pde pd
  * The h-norm is ||e||_h^2 = sum_K |J_K| sum_i W_i e_i^2 (GLL weights W_i).
  */
 ihdg_status ihdg_sweep(ihdg_ctx* ctx, int32_t n_sweeps, double* incr_norm);
+
+/*
+ * Run n_sweeps of the mixed path's FP32 correction sweeps
+ * delta <- d + G32 x(delta) (FP32 operators, FP32 state, the FP32 matrix
+ * cores or FP32 FMAs) on the context's correction state: zero after setup,
+ * the last correction after ihdg_solve.  incr_norm as in ihdg_sweep, of the
+ * correction.  IHDG_ERR_UNSUPPORTED unless the context is IHDG_MIXED.  For
+ * timing the FP32 sweep; the solution is not touched.
+ */
+ihdg_status ihdg_sweep32(ihdg_ctx* ctx, int32_t n_sweeps, double* incr_norm);
 
 /*
  * Iterate from the current iterate until ||u^k - u^{k-1}||_h <= tol ||u^k||_h

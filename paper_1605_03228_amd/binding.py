@@ -44,7 +44,7 @@ class Options(C.Structure):
     _fields_ = [("prec", C.c_int), ("check_every", C.c_int32), ("max_iters", C.c_int32),
                 ("krylov_restart", C.c_int32), ("inner_rtol", C.c_double), ("use_graph", C.c_int32),
                 ("force_per_element", C.c_int32), ("block_waves", C.c_int32), ("time_stepping", C.c_int32),
-                ("transport_flux", C.c_int32), ("krylov_method", C.c_int32)]
+                ("transport_flux", C.c_int32), ("krylov_method", C.c_int32), ("mixed_period", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -68,7 +68,7 @@ EXPORTS = ["ihdg_sizes", "ihdg_quadrature_points", "ihdg_footprint", "ihdg_setup
            "ihdg_get_stats", "ihdg_last_error", "ihdg_status_string", "ihdg_destroy",
            "ihdg_batch_footprint", "ihdg_batch_create", "ihdg_batch_add", "ihdg_batch_round",
            "ihdg_batch_poll", "ihdg_batch_use_graphs", "ihdg_batch_destroy", "ihdg_batch_last_error",
-           "ihdg_time_step", "ihdg_node_points", "ihdg_setup_noalloc"]
+           "ihdg_time_step", "ihdg_node_points", "ihdg_setup_noalloc", "ihdg_sweep32"]
 
 
 def load():
@@ -90,6 +90,7 @@ def load():
     lib.ihdg_setup_noalloc.argtypes = [P(Mesh), C.c_int32, C.c_int, P(Coeffs), P(Options), C.c_void_p, C.c_size_t,
                                        C.c_void_p, P(C.c_void_p)]
     lib.ihdg_sweep.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
+    lib.ihdg_sweep32.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
     lib.ihdg_solve.argtypes = [C.c_void_p, C.c_double, P(C.c_int32), P(C.c_double), P(C.c_double)]
     lib.ihdg_residual.argtypes = [C.c_void_p, P(C.c_double)]
     lib.ihdg_get_solution.argtypes = [C.c_void_p, C.c_void_p]
@@ -190,7 +191,8 @@ def _coeffs(c):
 
 
 def _options(prec=FP64, check_every=16, max_iters=0, krylov_restart=0, inner_rtol=0.0, use_graph=True,
-             force_per_element=False, block_waves=0, flux="upwind", time_stepping=False, krylov="gmres"):
+             force_per_element=False, block_waves=0, flux="upwind", time_stepping=False, krylov="gmres",
+             mixed_period=0):
     """krylov = "gmres" (GMRES(krylov_restart) when krylov_restart > 0) or
     "bicgstab" (selects the Krylov solve by itself)."""
     o = Options()
@@ -205,6 +207,7 @@ def _options(prec=FP64, check_every=16, max_iters=0, krylov_restart=0, inner_rto
     o.block_waves = block_waves
     o.transport_flux = {"upwind": 0, "npc": 1}[flux]
     o.time_stepping = 1 if time_stepping else 0
+    o.mixed_period = mixed_period
     return o
 
 
@@ -266,6 +269,12 @@ class Solver:
     def sweep(self, n=1, norms=False):
         out = (C.c_double * 2)()
         _check(self.lib.ihdg_sweep(self.ctx, n, out if norms else None), self.ctx)
+        return (out[0], out[1]) if norms else None
+
+    def sweep32(self, n=1, norms=False):
+        """n FP32 correction sweeps of a mixed-precision context (for timing)."""
+        out = (C.c_double * 2)()
+        _check(self.lib.ihdg_sweep32(self.ctx, n, out if norms else None), self.ctx)
         return (out[0], out[1]) if norms else None
 
     def solve(self, tol, raise_on_fail=False):

@@ -859,14 +859,47 @@ static ihdg_status solve_fp64(ihdg_ctx* c, double tol, int32_t* iters, double* f
   return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
 }
 
-// Mixed precision: defect correction.  Outer: FP64 defect d = psi(u) - u;
-// inner: FP32 sweeps  delta <- d + G32 x(delta)  until the relative increment
-// falls below inner_rtol (or stalls); then u += delta in FP64.
+// Mixed precision: defect correction.  Outer: FP64 defect d = psi(u) - u
+// (its norm is the convergence test); inner: FP32 sweeps
+// delta <- d + G32 x(delta), started at delta = d (the first sweep from
+// zero); then u += delta in FP64.  Because the sweep is affine, an outer step
+// of P inner sweeps advances the FP64 iteration by P + 1 sweeps, with FP32
+// rounding only in the product G32 x(delta), relative to the correction.
+// Re-anchoring every P sweeps (the default) keeps that rounding small at
+// every stage, so the solve takes about the FP64 sweep count; P < 0 runs each
+// correction until it stalls at the FP32 floor instead (the rounding of a
+// whole solve then spreads over the mesh and the next outer step has to
+// propagate it again).  Once the last defect is within kNear x tol, the FP32
+// increment (the iteration's own increment, u_k = anchor + delta_k) is read
+// after every round of check_every sweeps and a round whose increment meets
+// the tolerance, or is at the FP32 resolution of the correction, ends the
+// period early; the FP64 defect then decides.
+constexpr double kNear = 1e3;
+// An FP32 correction whose increment is below this fraction of the correction
+// itself is at its rounding floor.
+constexpr double kFloor32 = 1e-6;
+
+static int mixed_period(const ihdg_ctx* c) {
+  return c->opt.mixed_period == 0 ? 4 * c->opt.check_every : c->opt.mixed_period;
+}
+
+// Whether the coming correction reads its increment after every round: in the
+// first outer step (nothing is known of the contraction yet), within kNear x
+// tol, or when the contraction between the last two defects (dn_prev, `gap`
+// sweeps before dn) predicts the tolerance within the period.
+static bool mixed_check_rounds(int outer, double dn, double dn_prev, int64_t gap, int P, double tol, double un) {
+  if (outer == 0 || dn <= kNear * tol * un) return true;
+  if (!(dn_prev > 0) || gap <= 0 || !(dn < dn_prev)) return false;
+  const double rate = std::pow(dn / dn_prev, 1.0 / (double)gap);
+  return dn * std::pow(rate, (double)(P + 1)) <= tol * un;
+}
+
 static ihdg_status solve_mixed(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr) {
   const int S = c->opt.check_every;
-  int64_t total = 0;
-  double best = INFINITY;
-  for (int outer = 0; outer < 200; ++outer) {
+  const int P = mixed_period(c);
+  int64_t total = 0, at_prev = 0;
+  double best = INFINITY, dn_prev = 0.0;
+  for (int outer = 0; total < c->opt.max_iters; ++outer) {
     double dn, un;
     HIPCHK(c, defect64(c, &dn, &un));
     total += 1;
@@ -879,40 +912,63 @@ static ihdg_status solve_mixed(ihdg_ctx* c, double tol, int32_t* iters, double* 
     best = std::min(best, dn);
     if (dn > 1e3 * best) return fail(c, IHDG_ERR_DIVERGED, "defect grew 1e3x above its minimum");
     if (total >= c->opt.max_iters) return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
-    // inner tolerance: enough to bring the defect below tol ||u||, never below
-    // what FP32 can resolve (inner_rtol)
-    const double eta = std::max(c->opt.inner_rtol, std::min(0.1, 0.3 * tol * un / dn));
     HIPCHK(c, launch_diff_to_f32(c->tmp64, c->u64[c->cur], c->d32, c->nvec, c->stream));
-    HIPCHK(c, launch_fill_zero_f32(c->dl32[0], c->nvec, c->stream));
-    HIPCHK(c, launch_fill_zero_f32(c->dl32[1], c->nvec, c->stream));
     c->cur32 = 0;
-    double prev = INFINITY;
-    double ibest = INFINITY;
-    int stall = 0;
-    while (total < c->opt.max_iters) {
-      int n = (int)std::min<int64_t>(S, c->opt.max_iters - total);
-      HIPCHK(c, run_batch(c, true, n));
-      total += n;
-      c->stats.fp32_sweeps += n;
-      double h[2];
-      HIPCHK(c, read_norms(c, h));
-      double inc = std::sqrt(h[0]), nd = std::sqrt(h[1]);
-      if (!std::isfinite(inc)) return fail(c, IHDG_ERR_DIVERGED, "non-finite correction");
-      // enough for the FP64 tolerance, or resolved as far as needed relative to the correction
-      if (inc <= std::max(eta * nd, 0.3 * tol * un) || inc == 0.0) break;
-      ibest = std::min(ibest, inc);
-      if (inc > 1e3 * ibest) return fail(c, IHDG_ERR_DIVERGED, "correction diverged");
-      // FP32 rounding floor: the increment no longer decreases
-      if (inc > 0.9 * prev && inc < 1e-5 * nd) {
-        if (++stall >= 2) break;
-      } else {
-        stall = 0;
+    if (P > 0) {
+      // delta_1 = d; P more sweeps
+      HIPCHK(c, hipMemcpyAsync(c->dl32[0], c->d32, (size_t)c->nvec * 4, hipMemcpyDeviceToDevice, c->stream));
+      const bool near = mixed_check_rounds(outer, dn, dn_prev, total - at_prev, P, tol, un);
+      dn_prev = dn;
+      at_prev = total;
+      for (int done = 0; done < P && total < c->opt.max_iters;) {
+        const int n = (int)std::min<int64_t>({(int64_t)S, (int64_t)(P - done), c->opt.max_iters - total});
+        HIPCHK(c, run_batch(c, true, n));
+        total += n;
+        done += n;
+        c->stats.fp32_sweeps += n;
+        if (near) {
+          double h[2];
+          HIPCHK(c, read_norms(c, h));
+          const double inc = std::sqrt(h[0]), nd = std::sqrt(h[1]);
+          if (!std::isfinite(inc)) return fail(c, IHDG_ERR_DIVERGED, "non-finite correction");
+          // converged, or at the FP32 resolution of the correction: re-anchor
+          if (inc <= tol * un || inc < kFloor32 * nd) break;
+        }
       }
-      prev = inc;
+    } else {
+      // inner tolerance: enough to bring the defect below tol ||u||, never
+      // below what FP32 can resolve (inner_rtol)
+      const double eta = std::max(c->opt.inner_rtol, std::min(0.1, 0.3 * tol * un / dn));
+      HIPCHK(c, launch_fill_zero_f32(c->dl32[0], c->nvec, c->stream));
+      HIPCHK(c, launch_fill_zero_f32(c->dl32[1], c->nvec, c->stream));
+      double prev = INFINITY;
+      double ibest = INFINITY;
+      int stall = 0;
+      while (total < c->opt.max_iters) {
+        int n = (int)std::min<int64_t>(S, c->opt.max_iters - total);
+        HIPCHK(c, run_batch(c, true, n));
+        total += n;
+        c->stats.fp32_sweeps += n;
+        double h[2];
+        HIPCHK(c, read_norms(c, h));
+        double inc = std::sqrt(h[0]), nd = std::sqrt(h[1]);
+        if (!std::isfinite(inc)) return fail(c, IHDG_ERR_DIVERGED, "non-finite correction");
+        // enough for the FP64 tolerance, or resolved as far as needed relative to the correction
+        if (inc <= std::max(eta * nd, 0.3 * tol * un) || inc == 0.0) break;
+        ibest = std::min(ibest, inc);
+        if (inc > 1e3 * ibest) return fail(c, IHDG_ERR_DIVERGED, "correction diverged");
+        // FP32 rounding floor: the increment no longer decreases
+        if (inc > 0.9 * prev && inc < 1e-5 * nd) {
+          if (++stall >= 2) break;
+        } else {
+          stall = 0;
+        }
+        prev = inc;
+      }
     }
     HIPCHK(c, launch_add_f32_to_f64(c->u64[c->cur], c->dl32[c->cur32], c->nvec, c->stream));
   }
-  return fail(c, IHDG_ERR_MAXITER, "too many outer steps");
+  return fail(c, IHDG_ERR_MAXITER, "max_iters reached");
 }
 
 static ihdg_status solve_gmres(ihdg_ctx* c, double tol, int32_t* iters, double* final_incr);
@@ -925,6 +981,21 @@ ihdg_status ihdg_sweep(ihdg_ctx* c, int32_t n_sweeps, double* incr_norm) {
   if (n_sweeps == 0) return IHDG_OK;
   HIPCHK(c, run_batch(c, false, n_sweeps));
   c->stats.fp64_sweeps += n_sweeps;
+  if (incr_norm) {
+    double h[2];
+    HIPCHK(c, read_norms(c, h));
+    incr_norm[0] = std::sqrt(h[0]);
+    incr_norm[1] = std::sqrt(h[1]);
+  }
+  return IHDG_OK;
+}
+
+ihdg_status ihdg_sweep32(ihdg_ctx* c, int32_t n_sweeps, double* incr_norm) {
+  if (!c || n_sweeps < 0) return IHDG_ERR_ARG;
+  if (!c->mixed) return fail(c, IHDG_ERR_UNSUPPORTED, "FP32 sweeps need a mixed-precision context");
+  if (n_sweeps == 0) return IHDG_OK;
+  HIPCHK(c, run_batch(c, true, n_sweeps));
+  c->stats.fp32_sweeps += n_sweeps;
   if (incr_norm) {
     double h[2];
     HIPCHK(c, read_norms(c, h));
@@ -1302,6 +1373,10 @@ struct BMember {
   int64_t iters;
   double best, ibest, prev, eta, rel, unorm;
   int stall;
+  int inner;  // FP32 sweeps of the current correction
+  bool near;  // a converged round ends the correction (mixed_check_rounds)
+  double dn_prev;   // the previous defect norm, and the sweep count at it
+  int64_t at_prev;
 };
 
 }  // namespace
@@ -1612,21 +1687,33 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
       else {
         m.eta = std::max(c->opt.inner_rtol, std::min(0.1, 0.3 * m.tol * nrm / inc));
         m.unorm = nrm;
-        if (launch_diff_to_f32(c->tmp64, c->u64[c->cur], c->d32, c->nvec, st) != hipSuccess ||
-            launch_fill_zero_f32(c->dl32[0], c->nvec, st) != hipSuccess ||
-            launch_fill_zero_f32(c->dl32[1], c->nvec, st) != hipSuccess)
+        m.near = mixed_check_rounds(c->stats.outer_steps - 1, inc, m.dn_prev, m.iters - m.at_prev, mixed_period(c),
+                                    m.tol, nrm);
+        m.dn_prev = inc;
+        m.at_prev = m.iters;
+        if (launch_diff_to_f32(c->tmp64, c->u64[c->cur], c->d32, c->nvec, st) != hipSuccess) return IHDG_ERR_HIP;
+        if (mixed_period(c) > 0) {  // as solve_mixed: delta_1 = d, then the period's sweeps
+          if (hipMemcpyAsync(c->dl32[0], c->d32, (size_t)c->nvec * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return IHDG_ERR_HIP;
+        } else if (launch_fill_zero_f32(c->dl32[0], c->nvec, st) != hipSuccess ||
+                   launch_fill_zero_f32(c->dl32[1], c->nvec, st) != hipSuccess) {
           return IHDG_ERR_HIP;
+        }
         c->cur32 = 0;
         m.mode = kModeF32;
         m.ibest = m.prev = INFINITY;
         m.stall = 0;
+        m.inner = 0;
       }
     } else {
       m.iters += S;
       c->stats.fp32_sweeps += S;
       if (S % 2) c->cur32 ^= 1;
       bool stop = false;
+      m.inner += S;
+      const int P = mixed_period(c);
       if (!std::isfinite(inc)) status = IHDG_ERR_DIVERGED;
+      else if (P > 0) stop = m.inner >= P || (m.near && (inc <= m.tol * m.unorm || inc < kFloor32 * nrm));
       else if (inc <= std::max(m.eta * nrm, 0.3 * m.tol * m.unorm) || inc == 0.0) stop = true;
       else if (inc > 1e3 * (m.ibest = std::min(m.ibest, inc))) status = IHDG_ERR_DIVERGED;
       else {
