@@ -186,3 +186,65 @@ def test_paper_elliptic_table_pattern():
             assert got[(64, p, nu)] > k
         if nu == 1:
             assert abs(got[(n_el, p, 10)] - k) <= 0.15 * k
+
+
+def sweep_matrix(o):
+    """The linear part T of the oracle's sweep, psi(u) = T u + psi(0), as a sparse
+    matrix: a sweep couples an element only to itself and its face
+    neighbours, so elements coloured (i mod 3, j mod 3) have disjoint
+    footprints and 9 n_loc probing sweeps give every column exactly."""
+    import scipy.sparse as sp
+    mesh = o.mesh
+    nloc = o.m * o.el.np
+    n_el = mesh.n_el
+    c0 = o.sweep(np.zeros((n_el, nloc)))
+    ij = np.array([mesh.el_ijk(e)[:2] for e in range(n_el)])
+    colour = (ij[:, 0] % 3) + 3 * (ij[:, 1] % 3)
+    # footprint of element e: itself and its face neighbours
+    foot = {e: [e] + [nb for nb in (mesh.neighbour(e, f) for f in range(2 * mesh.dim)) if nb >= 0]
+            for e in range(n_el)}
+    rows, cols, vals = [], [], []
+    for col in range(9):
+        els = np.flatnonzero(colour == col)
+        for j in range(nloc):
+            v = np.zeros((n_el, nloc))
+            v[els, j] = 1.0
+            t = o.sweep(v) - c0
+            for e in els:
+                for r in foot[e]:
+                    nz = np.flatnonzero(t[r])
+                    rows.extend(r * nloc + nz)
+                    cols.extend([e * nloc + j] * len(nz))
+                    vals.extend(t[r, nz])
+    N = n_el * nloc
+    return sp.csc_matrix((vals, (rows, cols)), shape=(N, N)), c0
+
+
+@pytest.mark.parametrize("gamma,n,p", [(0.6, 8, 3), (1.0, 24, 2)], ids=["divergent_8x8_p3", "fine_24x24_p2"])
+def test_condition_of_the_krylov_operator(gamma, n, p):
+    """The conditioning of (I - T)u = c, the system the Krylov solves of the
+    elliptic regime run on (GPU tests in test_gpu_elliptic.py): T is built
+    exactly by probing, checked against a sweep of a random vector, and the
+    1-norm condition number is estimated (Hager-Higham, through an LU solve).
+    The error a solve leaves is at most kappa x its relative residual; the
+    measured values are recorded with the GPU results.  A zero-residual solve
+    of the probed system also reproduces the oracle's direct HDG solution,
+    which pins the probing."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    pr = w.cd_elliptic((n, n), p, gamma=gamma, nu=1.0)
+    o = CDOperators(pr)
+    T, c0 = sweep_matrix(o)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(c0.shape)
+    assert np.allclose(T @ v.ravel() + c0.ravel(), o.sweep(v).ravel(), rtol=0, atol=1e-11 * np.abs(o.sweep(v)).max())
+    A = (sp.identity(T.shape[0], format="csc") - T).tocsc()
+    lu = spla.splu(A)
+    ud = o.direct_hdg()
+    x = lu.solve(c0.ravel()).reshape(ud.shape)
+    assert rel(o, x, ud) < 1e-11
+    inv = spla.LinearOperator(A.shape, matvec=lu.solve, rmatvec=lambda y: lu.solve(y, trans="T"))
+    kappa = spla.onenormest(A) * spla.onenormest(inv)
+    print(f"gamma {gamma}, {n}x{n}, p = {p}: kappa_1(I - T) ~ {kappa:.3e}")
+    # the fine mesh is the worse conditioned one; both far from FP64's limit
+    assert 1.0 < kappa < 1e8
