@@ -18,7 +18,7 @@ being solved.  The loop
 Requests the plain iteration cannot solve (convection-diffusion with a
 diffusion coefficient in the region where the paper's Tables 3-4 show the
 iteration diverging, and the elliptic stabilisation) are routed at admission to
-a Krylov solve with the sweep as its operator (GMRES by default, BiCGStab on
+a Krylov solve with the sweep as its operator (BiCGStab by default, GMRES on
 request), run on a worker thread with a stream of its own so they overlap with
 the batch.  If a batched request diverges anyway it is re-queued for the
 Krylov path.
@@ -65,7 +65,7 @@ def needs_krylov(problem):
 class Server:
     def __init__(self, hbm_budget_bytes=64 << 30, sweeps=16, max_members=256, max_blocks=1 << 22,
                  device="cuda", krylov_workers=3, krylov_restart=40, keep_solutions=False, progress=0,
-                 setup_workers=2, krylov="gmres"):
+                 setup_workers=2, krylov="bicgstab"):
         self.budget = hbm_budget_bytes
         self.sweeps = sweeps
         self.max_members = max_members

@@ -38,7 +38,7 @@ def test_serving_all_converge_and_match_alone():
         rec = out["records"][rid]
         print(f"[gpu] alone {pr.name}", flush=True)
         if needs_krylov(pr):
-            s = make_solver(pr, krylov_restart=40, max_iters=200000)
+            s = make_solver(pr, krylov=srv.krylov, krylov_restart=40, max_iters=200000)
         else:
             s = make_solver(pr, prec=MIXED, check_every=16)
         res = s.solve(tol)
