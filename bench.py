@@ -99,12 +99,17 @@ KERNEL = {"cfg1": "k_sweep_mfma<double, transport, 2, 2>", "cfg2": "k_sweep<doub
           "cfg3": "k_sweep_mfma<double, transport, 3, 3>", "cfg4a": "k_sweep_mfma<double, shallow water, 2, 3>",
           "cfg4b": "k_sweep<double, conv.-diff., 2, 4, per-element>",
           "elliptic": "k_sweep_mfma<double, conv.-diff., 2, 3>"}
-# the matrix-core transport kernel without LDS staging (launch shape 5)
+# the matrix-core transport kernels without LDS staging of the traces: direct
+# (launch shape 5), staged GEMM (6) and own-tile (7, 3-D; the template's last
+# argument is the outflow mask of beta's signs)
 DIRECT = {"cfg1": "k_sweep_direct<double, 2, 2>", "cfg3": "k_sweep_direct<double, 3, 3>"}
+GEMM = {"cfg1": "k_sweep_gemm<double, 2, 2>", "cfg3": "k_sweep_gemm<double, 3, 3>"}
+OWN = {"cfg3": "k_sweep_own<double, 3, mask>"}
 
 
 def kernel_name(workload, waves):
-    return DIRECT[workload] if (waves == 5 and workload in DIRECT) else KERNEL[workload]
+    table = {5: DIRECT, 6: GEMM, 7: OWN}.get(waves, {})
+    return table.get(workload, KERNEL[workload])
 
 
 def make_problem(name):

@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libihdg.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["ref_tables.cpp", "ihdg_api.cpp", "setup_kernels.hip", "vector_ops.hip",
-           "sweep_transport.hip", "sweep_sw.hip", "sweep_cd.hip"]
+           "sweep_transport.hip", "sweep_own.hip", "sweep_sw.hip", "sweep_cd.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -67,6 +67,7 @@ struct ihdg_ctx {
   int cur32;
   int waves;    // launch shape of the FP64 sweep kernel (waves per block; 3 = vector-FMA shared variant)
   int waves32;  // same for the FP32 correction sweeps
+  int out_mask; // shared transport: bit a set when the outflow face of axis a is its high face (beta_a > 0)
   double sqrt_phi;
   hipGraphExec_t g64[2];
   hipGraphExec_t g32[2];
@@ -387,6 +388,9 @@ static ihdg_status setup_impl(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde
     case 6:
       if (!shared || pde != IHDG_TRANSPORT || !ihdg::gemm_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
       break;
+    case 7:
+      if (!shared || pde != IHDG_TRANSPORT || !ihdg::own_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
+      break;
     case 5:
       if (!shared) return IHDG_ERR_UNSUPPORTED;
       if (pde == IHDG_TRANSPORT && !ihdg::direct_supported(mi.dim, mi.p)) return IHDG_ERR_UNSUPPORTED;
@@ -443,6 +447,9 @@ static ihdg_status setup_impl(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde
   c->cur = 0;
   c->cur32 = 0;
   c->sqrt_phi = pde == IHDG_SHALLOW_WATER ? std::sqrt(coeffs->Phi) : 0.0;
+  c->out_mask = 0;
+  if (pde == IHDG_TRANSPORT && shared)  // a tangential axis (beta_a = 0) has zero weight on both faces
+    for (int ax = 0; ax < mi.dim; ++ax) c->out_mask |= (coeffs->beta_const[ax] >= 0.0 ? 1 : 0) << ax;
   c->waves = o.block_waves > 0 ? o.block_waves : 4;
   c->waves32 = c->waves;
   c->g64[0] = c->g64[1] = c->g32[0] = c->g32[1] = nullptr;
@@ -650,6 +657,7 @@ static hipError_t one_sweep(ihdg_ctx* c, bool fp32, const void* uin, void* uout,
   a.n_blk = c->mi.n_blk;
   a.n_el = c->mi.n_el;
   a.sqrt_phi = c->sqrt_phi;
+  a.shape_arg = c->out_mask;
   return ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, fp32 ? c->waves32 : c->waves, a,
                             c->stream);
 }
@@ -688,6 +696,7 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best, bool timed) {
   std::vector<int> cand = c->shared ? std::vector<int>{4, 8, 3} : std::vector<int>{1, 2, 4, 8};
   if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::direct_supported(c->mi.dim, c->mi.p)) cand.push_back(5);
   if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::gemm_supported(c->mi.dim, c->mi.p)) cand.push_back(6);
+  if (c->shared && c->pde == IHDG_TRANSPORT && ihdg::own_supported(c->mi.dim, c->mi.p)) cand.push_back(7);
   if (c->shared && c->pde == IHDG_CONVDIFF && ihdg::direct_cd_supported(c->mi.p)) cand.push_back(5);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   struct Events {  // destroyed on every return path
@@ -721,6 +730,7 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best, bool timed) {
     a.n_blk = nb;
     a.n_el = c->mi.n_el;
     a.sqrt_phi = c->sqrt_phi;
+    a.shape_arg = c->out_mask;
     for (int i = 0; i < 2; ++i)
       if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, a, c->stream)) != hipSuccess)
         return e;
@@ -1570,6 +1580,7 @@ ihdg_status ihdg_batch_round(ihdg_batch* b, int32_t sweeps, int32_t* n_active) {
       d.n_el = c->mi.n_el;
       d.blk0 = g.nb;
       d.sqrt_phi = c->sqrt_phi;
+      d.shape_arg = c->out_mask;
       for (int64_t k = 0; k < c->mi.n_blk; ++k) ho.push_back(local);
       g.nb += c->mi.n_blk;
       hd.push_back(d);

@@ -58,6 +58,7 @@ struct SweepArgs {
   int64_t n_blk;
   int64_t n_el;         // elements (the last block's lanes past it are padding)
   double sqrt_phi;      // shallow water sqrt(Phi)
+  int shape_arg;        // own-tile transport kernel: the outflow mask (bit a: high face of axis a)
 };
 
 // One member of a batched sweep: its buffers, its first block in the bucket's
@@ -75,7 +76,7 @@ struct BatchDesc {
   int64_t blk0;
   double sqrt_phi;
   int parity0;
-  int pad_;
+  int shape_arg;  // as SweepArgs::shape_arg
 };
 
 __host__ __device__ inline SweepArgs batch_args(const BatchDesc& d, int s) {
@@ -92,6 +93,7 @@ __host__ __device__ inline SweepArgs batch_args(const BatchDesc& d, int s) {
   a.n_blk = d.n_blk;
   a.n_el = d.n_el;
   a.sqrt_phi = d.sqrt_phi;
+  a.shape_arg = d.shape_arg;
   return a;
 }
 
@@ -125,6 +127,12 @@ bool direct_supported(int dim, int p);
 bool gemm_supported(int dim, int p);
 // the convection-diffusion direct kernel (launch shape 5, shared operator, 2-D) fits for order p
 bool direct_cd_supported(int p);
+// True where the transport own-tile variant (launch shape 7, shared operators
+// in 3-D) has an instance; its launches take the outflow mask in shape_arg.
+bool own_supported(int dim, int p);
+hipError_t launch_own(int dim, int p, bool fp32, const SweepArgs& a, hipStream_t s);
+hipError_t launch_own_batched(int dim, int p, bool fp32, const BatchDesc* d, const int* owner, int64_t nb, int sidx,
+                              hipStream_t s);
 
 hipError_t launch_sweep_batched_transport(int dim, int p, bool fp32, bool shared, int waves, const BatchDesc* d,
                                           const int* owner, int64_t nb, int sidx, hipStream_t s);

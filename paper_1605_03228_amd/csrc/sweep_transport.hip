@@ -134,6 +134,7 @@ hipError_t launch_sweep_transport(int dim, int p, bool fp32, bool shared, int wa
                                   hipStream_t s) {
   if (waves == 5) return shared ? launch_direct_any(dim, p, fp32, a, s) : hipErrorNotSupported;
   if (waves == 6) return shared ? launch_gemm_any(dim, p, fp32, a, s) : hipErrorNotSupported;
+  if (waves == 7) return shared ? launch_own(dim, p, fp32, a, s) : hipErrorNotSupported;
   if (dim == 2) {
     switch (p) {
       case 1: return launch_variants<kTransport, 2, 1>(fp32, shared, waves, a, s);
@@ -158,6 +159,7 @@ hipError_t launch_sweep_batched_transport(int dim, int p, bool fp32, bool shared
                                           const int* owner, int64_t nb, int sidx, hipStream_t s) {
   if (waves == 5) return shared ? launch_direct_batched_any(dim, p, fp32, d, owner, nb, sidx, s) : hipErrorNotSupported;
   if (waves == 6) return shared ? launch_gemm_batched_any(dim, p, fp32, d, owner, nb, sidx, s) : hipErrorNotSupported;
+  if (waves == 7) return shared ? launch_own_batched(dim, p, fp32, d, owner, nb, sidx, s) : hipErrorNotSupported;
   if (dim == 2) {
     switch (p) {
       case 1: return launch_variants_batched<kTransport, 2, 1>(fp32, shared, waves, d, owner, nb, sidx, s);

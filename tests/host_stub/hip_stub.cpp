@@ -210,6 +210,11 @@ hipError_t launch_sweep_sw(int, bool, bool, int, const SweepArgs&, hipStream_t s
 hipError_t launch_sweep_cd(int, bool, bool, int, const SweepArgs&, hipStream_t s) { return nop(s); }
 bool direct_supported(int, int) { return true; }
 bool gemm_supported(int, int) { return true; }
+bool own_supported(int, int) { return true; }
+hipError_t launch_own(int, int, bool, const SweepArgs&, hipStream_t s) { return nop(s); }
+hipError_t launch_own_batched(int, int, bool, const BatchDesc*, const int*, int64_t, int, hipStream_t s) {
+  return nop(s);
+}
 hipError_t noalloc_scratch(hipStream_t, void** out) {
   static void* buf = std::malloc(kNoAllocScratchBytes);
   if (inject()) return fail_with(hipErrorUnknown);

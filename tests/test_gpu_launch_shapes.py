@@ -10,7 +10,10 @@ several 64-element blocks with a ragged last block:
   straight from the iterate, no LDS staging; for convection-diffusion the
   face projection is folded into the operator), 6 (transport: the block's
   iterate and its inflow halo staged once in LDS, G in registers, persistent
-  with the next block's loads in flight).
+  with the next block's loads in flight), 7 (3-D transport: the element's own
+  u^k tile as the matrix cores' operand for the outflow faces, one instance
+  per outflow side of each axis: all eight sign patterns of beta and a
+  tangential axis are run).
 
 Bar: one sweep is an affine map applied in FP64, so after a few sweeps the
 iterates agree with the oracle's to rounding (1e-12 relative in the h-norm);
@@ -65,6 +68,19 @@ SHARED = [
     ("3d_5cube_p3", lambda: w.config3(n=5, p=3)),
 ]
 SHAPES = [(name, make, wv, {}) for name, make in SHARED for wv in (3, 4, 5, 6, 8)]
+SHAPES += [(name, make, 7, {}) for name, make in SHARED[2:]]
+# launch shape 7 over every outflow mask (bit a: beta_a > 0), a tangential axis,
+# each order, ragged last blocks
+OWN_CASES = [(f"3d_5cube_p3_mask{m}",
+              (lambda m=m: w.transport_const((5, 5, 5), 3, (0.6 if m & 1 else -0.6, 0.48 if m & 2 else -0.48,
+                                                            0.64 if m & 4 else -0.64), exact="u3")))
+             for m in range(8)]
+OWN_CASES += [("3d_6x5x4_p3_tangential_x", lambda: w.transport_const((6, 5, 4), 3, (0.0, 0.6, -0.8), exact="u3")),
+              ("3d_4x6x5_p3_tangential_z", lambda: w.transport_const((4, 6, 5), 3, (-0.8, 0.6, 0.0), exact="u3")),
+              ("3d_7x6x5_p2_mask5", lambda: w.transport_const((7, 6, 5), 2, (0.6, -0.48, 0.64), exact="u3")),
+              ("3d_9x8x7_p1_mask2", lambda: w.transport_const((9, 8, 7), 1, (-0.6, 0.48, -0.64), exact="u3"))]
+SHAPES += [(name, make, 7, {}) for name, make in OWN_CASES]
+SHAPES += [(name + "_npc", make, 7, {"flux": "npc"}) for name, make in OWN_CASES[:8:3]]
 SHAPES += [("cfg2_13x11_p3_per_el", _ragged_cfg2, wv, {}) for wv in (1, 2, 4, 8)]
 SHAPES += [("3d_4cube_p4_shared", lambda: w.config3(n=4, p=4), wv, {}) for wv in (3, 4, 8)]
 CD_SHARED = [
@@ -77,14 +93,14 @@ CD_SHARED = [
 SHAPES += [(name, make, wv, {}) for name, make in CD_SHARED for wv in (3, 4, 5, 8)]
 
 
-def _oracle(pr):
-    return CDOperators(pr) if pr.pde == "cd" else TransportOperators(pr)
+def _oracle(pr, flux="upwind"):
+    return CDOperators(pr) if pr.pde == "cd" else TransportOperators(pr, flux=flux)
 
 
 @pytest.mark.parametrize("name,make,waves,kw", SHAPES, ids=[f"{c[0]}-w{c[2]}" for c in SHAPES])
 def test_launch_shape_per_sweep(name, make, waves, kw):
     pr = make()
-    o = _oracle(pr)
+    o = _oracle(pr, kw.get("flux", "upwind"))
     s = _solver(pr, block_waves=waves, **kw)
     assert s.stats()["kernel_waves"] == waves
     u = np.zeros((o.mesh.n_el, s.sz["n_loc"]))
@@ -106,6 +122,27 @@ def test_direct_variant_mixed_precision_solve(name, make):
     pr = make()
     o = _oracle(pr)
     s = _solver(pr, block_waves=5, prec=1)
+    res = s.solve(1e-10)
+    assert res["status"] == 0, res
+    ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
+    assert _rel(o, _u(s), ref) < 1e-8
+    s.close()
+
+
+@pytest.mark.parametrize("name,make", [SHARED[4], OWN_CASES[6], OWN_CASES[9]],
+                         ids=[SHARED[4][0], OWN_CASES[6][0], OWN_CASES[9][0]])
+def test_own_tile_variant_solves(name, make):
+    """FP64 and mixed solves on the own-tile kernel (7) reach the oracle's
+    downwind solution (1e-10 / 1e-8)."""
+    pr = make()
+    o = _oracle(pr)
+    ref = o.downwind()
+    s = _solver(pr, block_waves=7)
+    res = s.solve(1e-12)
+    assert res["status"] == 0, res
+    assert _rel(o, _u(s), ref) < 1e-10
+    s.close()
+    s = _solver(pr, block_waves=7, prec=1)
     res = s.solve(1e-10)
     assert res["status"] == 0, res
     ref = o.downwind() if pr.pde == "transport" else o.direct_hdg()
@@ -152,13 +189,16 @@ def test_staged_gemm_equals_direct_bitwise(name, make):
     b.close()
 
 
-@pytest.mark.parametrize("waves", [5, 6])
+@pytest.mark.parametrize("waves", [5, 6, 7])
 def test_direct_variant_batched_equals_single_bitwise(waves):
     from paper_1605_03228_amd import Batch
     items = [w.config3(n=5, p=3), w.transport_const((19, 13), 2, (1.0, 0.5)), w.config3(seed=2, n=6, p=3),
              w.cd_poly((17, 9), 2, kappa=0.3, affine_beta=False), w.cd_elliptic((5, 7), 3, gamma=1.0, nu=1.0)]
     if waves == 6:  # the staged-GEMM kernel is transport-only
         items = items[:3] + [w.config3(seed=3, n=7, p=2), w.config3(seed=4, n=9, p=1)]
+    if waves == 7:  # the own-tile kernel: 3-D transport, members of different outflow masks
+        items = [w.config3(n=5, p=3), w.config3(seed=2, n=6, p=3), w.config3(seed=5, n=4, p=3),
+                 w.config3(seed=3, n=7, p=2), w.config3(seed=4, n=9, p=1), OWN_CASES[8][1]()]
     singles = []
     for pr in items:
         s = _solver(pr, block_waves=waves)
@@ -193,7 +233,11 @@ def test_launch_shape_validation():
              (w.cd_elliptic((4, 4), 3, gamma=1.0), 6, 2),         # staged GEMM: transport only
              (w.config3(n=3, p=4), 6, 2),                         # staged GEMM: no 3-D p = 4 instance
              (_ragged_cfg2(), 6, 2),                              # staged GEMM: shared operators only
-             (w.config1(), 7, 1), (w.config1(), -1, 1)]           # not a launch shape
+             (w.config1(), 7, 2),                                 # own-tile: 3-D only
+             (w.config3(n=3, p=4), 7, 2),                         # own-tile: no 3-D p = 4 instance
+             (w.cd_elliptic((4, 4), 3, gamma=1.0), 7, 2),         # own-tile: transport only
+             (_ragged_cfg2(), 7, 2),                              # own-tile: shared operators only
+             (w.config1(), 9, 1), (w.config1(), -1, 1)]           # not a launch shape
     for pr, wv, status in cases:
         with pytest.raises(IhdgError) as e:
             _solver(pr, block_waves=wv)
