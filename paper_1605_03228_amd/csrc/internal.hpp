@@ -32,6 +32,7 @@ struct SetupArgs {
   int pde, m, n_loc, n_in, m_f;
   int flux;         // transport: 0 upwind, 1 NPC
   int shared_rep;   // 1: assemble one representative element, all faces treated as interior
+  int assembled;    // 1: the augmented matrix is already in scratch (k_setup only eliminates)
   int64_t e0;       // first element of this chunk
   int64_t count;    // elements in this chunk
   double* scratch;  // count x n_loc x ncol augmented matrices

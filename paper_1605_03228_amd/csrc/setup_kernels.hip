@@ -483,14 +483,16 @@ __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
   load_element(a, e, rep, d);
   const int n = a.n_loc, ni = a.n_in, nc = a.ncol;
   double* A = a.scratch + le * (int64_t)n * nc;
-  for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
-    int r = idx / nc, col = idx % nc;
-    double v;
-    if (col < n) v = entry_L(a, b, d, r, col);
-    else if (col < n + ni) v = entry_E(a, b, d, r, col - n);
-    else if (!rep) v = entry_F(a, b, d, r);
-    else v = (col - n - ni == r) ? 1.0 : 0.0;  // identity: L^{-1}
-    A[idx] = v;
+  if (!a.assembled) {
+    for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
+      int r = idx / nc, col = idx % nc;
+      double v;
+      if (col < n) v = entry_L(a, b, d, r, col);
+      else if (col < n + ni) v = entry_E(a, b, d, r, col - n);
+      else if (!rep) v = entry_F(a, b, d, r);
+      else v = (col - n - ni == r) ? 1.0 : 0.0;  // identity: L^{-1}
+      A[idx] = v;
+    }
   }
   // conv.-diff. face projections
   if (a.pde == kConvDiff && threadIdx.x < m.nf) {
@@ -539,21 +541,115 @@ __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
   }
 }
 
-// Shared operator: c_K = L^{-1} F_K for every element (F_K assembled per element).
+// Shared operator: c_K = L^{-1} F_K for every element.  The volume part of
+// F_K, (f, l_i)_K for the rows that carry a forcing, is contracted from the
+// weighted forcing at the quadrature points one axis at a time (sum
+// factorisation on the tensor-product element: n1 nq1^2 + n1^2 nq1 + n1^3
+// products in 3-D instead of nq per row); the boundary part (the same face
+// terms as entry_F) comes from the element's boundary faces only.
 __global__ __launch_bounds__(kST) void k_shared_c(SetupArgs a) {
   __shared__ RefTab rt;
-  __shared__ ElemData d;
+  __shared__ double g0[kMaxNq];
+  __shared__ double t1[kMaxNq];
+  __shared__ double t2[kMaxNq];
   __shared__ double F[kMaxNloc];
+  __shared__ double bnf[kMaxNf][kMaxNfq];
+  __shared__ double gf[kMaxNf][kMaxNfq];
+  __shared__ int bdry[kMaxNf];
   if (threadIdx.x == 0) rt = a.rt;
-  __syncthreads();
   const MeshInfo& m = a.mi;
+  const Coeffs& c = a.cf;
   const int64_t e = a.e0 + blockIdx.x;
   if ((int64_t)blockIdx.x >= a.count) return;
-  Basis b(rt, m);
-  load_element(a, e, false, d);
-  const int n = a.n_loc;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) F[r] = entry_F(a, b, d, r);
+  const int n = a.n_loc, np = m.np, dim = m.dim, n1 = m.n1, nq1 = m.nq1, nq = m.nq;
+  int ijk[3];
+  el_ijk(m, e, ijk);
+  for (int r = threadIdx.x; r < n; r += blockDim.x) F[r] = 0.0;
+  if (threadIdx.x < m.nf) bdry[threadIdx.x] = neighbour(m, ijk, threadIdx.x) < 0;
   __syncthreads();
+  Basis b(rt, m);
+  for (int comp = 0; comp < a.m_f; ++comp) {
+    // the forcing's rows: shallow water field comp, transport u, conv.-diff. u
+    const int fi = a.pde == kShallowWater ? comp : (a.pde == kTransport ? 0 : dim);
+    for (int q = threadIdx.x; q < nq; q += blockDim.x)
+      g0[q] = b.W(q) * (c.f_q ? c.f_q[(e * nq + q) * a.m_f + comp] : 0.0);
+    __syncthreads();
+    if (dim == 3) {
+      // t1[i0 + n1 (q1 + nq1 q2)] = sum_q0 L[q0][i0] g0[q0 + nq1 (q1 + nq1 q2)]
+      for (int k = threadIdx.x; k < n1 * nq1 * nq1; k += blockDim.x) {
+        const int i0 = k % n1, q12 = k / n1;
+        double v = 0.0;
+        for (int q0 = 0; q0 < nq1; ++q0) v += rt.L[q0][i0] * g0[q0 + nq1 * q12];
+        t1[k] = v;
+      }
+      __syncthreads();
+      // t2[i0 + n1 (i1 + n1 q2)] = sum_q1 L[q1][i1] t1[i0 + n1 (q1 + nq1 q2)]
+      for (int k = threadIdx.x; k < n1 * n1 * nq1; k += blockDim.x) {
+        const int i0 = k % n1, i1 = (k / n1) % n1, q2 = k / (n1 * n1);
+        double v = 0.0;
+        for (int q1 = 0; q1 < nq1; ++q1) v += rt.L[q1][i1] * t1[i0 + n1 * (q1 + nq1 * q2)];
+        t2[k] = v;
+      }
+      __syncthreads();
+      // F[i0 + n1 (i1 + n1 i2)] += sum_q2 L[q2][i2] t2[i0 + n1 (i1 + n1 q2)]
+      for (int k = threadIdx.x; k < np; k += blockDim.x) {
+        const int i01 = k % (n1 * n1), i2 = k / (n1 * n1);
+        double v = 0.0;
+        for (int q2 = 0; q2 < nq1; ++q2) v += rt.L[q2][i2] * t2[i01 + n1 * n1 * q2];
+        F[fi * np + k] += v;
+      }
+    } else {
+      // t1[i0 + n1 q1] = sum_q0 L[q0][i0] g0[q0 + nq1 q1]
+      for (int k = threadIdx.x; k < n1 * nq1; k += blockDim.x) {
+        const int i0 = k % n1, q1 = k / n1;
+        double v = 0.0;
+        for (int q0 = 0; q0 < nq1; ++q0) v += rt.L[q0][i0] * g0[q0 + nq1 * q1];
+        t1[k] = v;
+      }
+      __syncthreads();
+      for (int k = threadIdx.x; k < np; k += blockDim.x) {
+        const int i0 = k % n1, i1 = k / n1;
+        double v = 0.0;
+        for (int q1 = 0; q1 < nq1; ++q1) v += rt.L[q1][i1] * t1[i0 + n1 * q1];
+        F[fi * np + k] += v;
+      }
+    }
+    __syncthreads();
+  }
+  // boundary data on the element's boundary faces (shallow water: walls, none)
+  if (a.pde != kShallowWater) {
+    bool any = false;
+    for (int f = 0; f < m.nf; ++f) any |= bdry[f] != 0;
+    if (any) {
+      for (int k = threadIdx.x; k < m.nf * m.nfq; k += blockDim.x) {
+        const int f = k / m.nfq, qf = k % m.nfq, ax = f >> 1;
+        const int64_t fid = face_id(m, ijk, f);
+        bnf[f][qf] = face_sign(f) * (c.bn_fq ? c.bn_fq[fid * m.nfq + qf] : c.beta_const[ax]);
+        gf[f][qf] = c.g_fq ? c.g_fq[fid * m.nfq + qf] : 0.0;
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const int fi = r / np, ni = r % np;
+        double v = 0.0;
+        for (int f = 0; f < m.nf; ++f) {
+          if (!bdry[f] || !b.on_face(f, ni)) continue;
+          const int ax = f >> 1;
+          for (int qf = 0; qf < m.nfq; ++qf) {
+            const double bn = bnf[f][qf], wq = b.Wf(f, qf) * b.Bf(f, qf, ni) * gf[f][qf];
+            if (a.pde == kTransport) {
+              v += wq * fmax(-bn, 0.0);             // |beta.n| g on inflow points
+            } else if (fi < dim) {
+              if (fi == ax) v -= face_sign(f) * wq;  // -<g, t . n>
+            } else {
+              v += wq * tau_cd(bn, c.tau_star);     // <tau g, v>
+            }
+          }
+        }
+        F[r] += v;
+      }
+      __syncthreads();
+    }
+  }
   const int64_t blk = e / kLanes;
   const int lane = (int)(e % kLanes);
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
@@ -701,8 +797,38 @@ hipError_t launch_node_points(const MeshInfo& mi, const RefTab& rt, double* x, h
 // them for 2-D p <= 5 and 3-D p = 1 (at 2-D p = 5, 43 KB, two workgroups fit
 // per CU instead of four, and the tables still halve the assembly's work),
 // the values without the derivatives for 2-D p = 6 and 3-D p = 2.
+// The augmented matrix of the representative element of a shared operator,
+// one entry per thread over as many workgroups as it takes (the same entry
+// functions as k_setup, so the same values); k_setup then only eliminates.
+__global__ __launch_bounds__(kST) void k_assemble_rep(SetupArgs a) {
+  __shared__ RefTab rt;
+  __shared__ ElemData d;
+  if (threadIdx.x == 0) rt = a.rt;
+  __syncthreads();
+  Basis b(rt, a.mi);
+  load_element(a, a.e0, true, d);
+  const int n = a.n_loc, ni = a.n_in, nc = a.ncol;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * nc) return;
+  const int r = (int)(idx / nc), col = (int)(idx % nc);
+  double v;
+  if (col < n) v = entry_L(a, b, d, r, col);
+  else if (col < n + ni) v = entry_E(a, b, d, r, col - n);
+  else v = (col - n - ni == r) ? 1.0 : 0.0;  // identity: L^{-1}
+  a.scratch[idx] = v;
+}
+
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   if (a.count <= 0) return hipSuccess;
+  if (a.shared_rep && a.count == 1) {
+    const int64_t total = (int64_t)a.n_loc * a.ncol;
+    hipLaunchKernelGGL(k_assemble_rep, dim3((unsigned)((total + kST - 1) / kST)), dim3(kST), 0, s, a);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    SetupArgs b = a;
+    b.assembled = 1;
+    hipLaunchKernelGGL(k_setup<0>, dim3(1), dim3(kST), 0, s, b);
+    return hipGetLastError();
+  }
   const size_t nq = (size_t)a.mi.nq, np = (size_t)a.mi.np;
   const size_t full = nq * (1 + (size_t)(1 + a.mi.dim) * np) * sizeof(double);
   const size_t wb = nq * (1 + np) * sizeof(double);

@@ -242,3 +242,35 @@ def test_launch_shape_validation():
         with pytest.raises(IhdgError) as e:
             _solver(pr, block_waves=wv)
         assert e.value.status == status, (pr.name, wv)
+
+
+def test_own_tile_mixed_batched_equals_alone_bitwise():
+    """Mixed solves on the own-tile kernel (FP64 and FP32 sweeps; persistent
+    when alone, one workgroup per block in a batch) give the same iterates
+    alone and batched, bit for bit, for members of different outflow masks
+    and orders."""
+    from paper_1605_03228_amd import Batch
+    items = [w.config3(n=5, p=3), w.config3(seed=2, n=7, p=3), w.config3(seed=5, n=4, p=3),
+             w.config3(seed=3, n=7, p=2), w.config3(seed=4, n=9, p=1), OWN_CASES[8][1]()]
+    singles = []
+    for pr in items:
+        s = _solver(pr, block_waves=7, prec=1)
+        res = s.solve(1e-10)
+        assert res["status"] == 0, res
+        singles.append((res["iters"], _u(s)))
+        s.close()
+    b = Batch(max_members=8)
+    for i, pr in enumerate(items):
+        b.add(_solver(pr, block_waves=7, prec=1), 1e-10, i)
+    got = {}
+    for _ in range(100000):
+        n = b.round(16)
+        for r in b.poll():
+            got[r["tag"]] = (r["iters"], _u(r["solver"]))
+            r["solver"].close()
+        if n == 0:
+            break
+    b.close()
+    for i in range(len(items)):
+        assert got[i][0] == singles[i][0], i
+        assert np.array_equal(got[i][1], singles[i][1]), i
