@@ -23,6 +23,8 @@ constexpr int kMaxNfq = 36;   // (p+2)^2 for p = 4
 constexpr int kMaxNloc = 147; // 3 x 7^2
 constexpr int kMaxNf = 6;
 constexpr int kST = 256;      // threads per setup workgroup
+constexpr int kMaxSfNq = 64;  // 2-D quadrature points, (p+2)^2 for p = 6
+constexpr int kMaxSfT = 392;  // 2-D sum-factorisation buffer, (p+2)(p+1)^2 for p = 6
 
 // ---------------------------------------------------------------------------
 // reference basis evaluated from the 1-D tables (tensor products)
@@ -255,6 +257,109 @@ __device__ double entry_L(const SetupArgs& a, const Basis& b, const ElemData& d,
   return v;
 }
 
+// The face terms of entry_L alone (transport and convection-diffusion), for
+// the assembly that forms the volume terms by sum factorisation.
+__device__ double entry_L_face(const SetupArgs& a, const Basis& b, const ElemData& d, int row, int col) {
+  const int np = a.mi.np, dim = a.mi.dim;
+  const int fi = row / np, ni = row % np, fj = col / np, nj = col % np;
+  const Coeffs& c = a.cf;
+  double v = 0.0;
+  if (a.pde == kTransport) {
+    const double cf = a.flux == 1 ? 1.0 : 2.0;
+    for (int f = 0; f < a.mi.nf; ++f) {
+      if (!b.on_face(f, ni) || !b.on_face(f, nj)) continue;
+      for (int qf = 0; qf < a.mi.nfq; ++qf) {
+        double bn = d.bn[f][qf];
+        v += b.Wf(f, qf) * cf * fmax(bn, 0.0) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+      }
+    }
+    return v;
+  }
+  if (fi < dim) return 0.0;
+  if (fj < dim) {
+    for (int f = 0; f < a.mi.nf; ++f)
+      if ((f >> 1) == fj) v += face_sign(f) * face_mass(b, f, ni, nj, nullptr);  // <s . n, v>
+    return v;
+  }
+  for (int f = 0; f < a.mi.nf; ++f) {
+    if (!b.on_face(f, ni) || !b.on_face(f, nj)) continue;
+    for (int qf = 0; qf < a.mi.nfq; ++qf) {
+      double bn = d.bn[f][qf];
+      v += b.Wf(f, qf) * (bn + tau_cd(bn, c.tau_star)) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+    }
+  }
+  return v;
+}
+
+// Sum factorisation on the 2-D tensor-product element: adds
+//   sum_q cq[q] X(q, i) Y(q, j),  X = X_0 (x) X_1,  Y = Y_0 (x) Y_1,
+// to block (rowoff + i, coloff + j) of the row-major matrix A (nc columns),
+// where X_b is the 1-D basis (or its physical derivative when b == xd) at the
+// 1-D points, Y_b likewise with yd; q = q0 + nq1 q1, i = i0 + n1 i1.
+// First T[q1][i0][j0] = sum_q0 cq X_0 Y_0, then the q1 sum: n1^2 nq1^2 +
+// n1^4 nq1 products in place of n1^4 nq1^2.
+__device__ void sf_add_2d(const RefTab& rt, const MeshInfo& m, const double* cq, int xd, int yd, double* T,
+                          double* A, int nc, int rowoff, int coloff) {
+  const int n1 = m.n1, nq1 = m.nq1, np = m.np;
+  const double sx0 = xd == 0 ? 2.0 / m.h[0] : 1.0, sx1 = xd == 1 ? 2.0 / m.h[1] : 1.0;
+  const double sy0 = yd == 0 ? 2.0 / m.h[0] : 1.0, sy1 = yd == 1 ? 2.0 / m.h[1] : 1.0;
+  for (int k = threadIdx.x; k < nq1 * n1 * n1; k += blockDim.x) {
+    const int j0 = k % n1, i0 = (k / n1) % n1, q1 = k / (n1 * n1);
+    double v = 0.0;
+    for (int q0 = 0; q0 < nq1; ++q0) {
+      const double x = xd == 0 ? sx0 * rt.dL[q0][i0] : rt.L[q0][i0];
+      const double y = yd == 0 ? sy0 * rt.dL[q0][j0] : rt.L[q0][j0];
+      v += cq[q0 + nq1 * q1] * x * y;
+    }
+    T[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < np * np; k += blockDim.x) {
+    const int i = k / np, j = k % np;
+    const int i0 = i % n1, i1 = i / n1, j0 = j % n1, j1 = j / n1;
+    double v = 0.0;
+    for (int q1 = 0; q1 < nq1; ++q1) {
+      const double x = xd == 1 ? sx1 * rt.dL[q1][i1] : rt.L[q1][i1];
+      const double y = yd == 1 ? sy1 * rt.dL[q1][j1] : rt.L[q1][j1];
+      v += x * y * T[(q1 * n1 + i0) * n1 + j0];
+    }
+    A[(int64_t)(rowoff + i) * nc + coloff + j] += v;
+  }
+  __syncthreads();
+}
+
+// Volume terms of L for one element (2-D transport and convection-diffusion),
+// added to A, term by term as in entry_L: the coefficient of each term at the
+// quadrature points goes to cq (LDS), then sf_add_2d.
+__device__ void assemble_volume_2d(const SetupArgs& a, const Basis& b, const RefTab& rt, const ElemData& d,
+                                   double* A, int nc, double* cq, double* T) {
+  const MeshInfo& m = a.mi;
+  const int np = m.np, nq = m.nq, dim = 2;
+  const Coeffs& c = a.cf;
+  const int uo = a.pde == kTransport ? 0 : dim * np;  // offset of the u block
+  // convection: -(u, beta . grad v) per axis, and -(u, (div beta) v) + (sigma or nu) (u, v)
+  for (int ax = 0; ax < dim; ++ax) {
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) cq[q] = -b.W(q) * d.beta[q][ax];
+    __syncthreads();
+    sf_add_2d(rt, m, cq, ax, -1, T, A, nc, uo, uo);
+  }
+  const double react = a.pde == kTransport ? d.sigma : c.nu;
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) cq[q] = b.W(q) * (react - d.divb[q]);
+  __syncthreads();
+  sf_add_2d(rt, m, cq, -1, -1, T, A, nc, uo, uo);
+  if (a.pde == kTransport) return;
+  // conv.-diff. flux blocks: (s_a, t_a) / kappa, -(u, d_a t_a), -(s_a, d_a v)
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) cq[q] = b.W(q) / c.kappa;
+  __syncthreads();
+  for (int ax = 0; ax < dim; ++ax) sf_add_2d(rt, m, cq, -1, -1, T, A, nc, ax * np, ax * np);
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) cq[q] = -b.W(q);
+  __syncthreads();
+  for (int ax = 0; ax < dim; ++ax) {
+    sf_add_2d(rt, m, cq, ax, -1, T, A, nc, ax * np, uo);  // -(u, d_a t_a): test derivative
+    sf_add_2d(rt, m, cq, ax, -1, T, A, nc, uo, ax * np);  // -(s_a, d_a v)
+  }
+}
+
 // E: column k = f * nfp + t feeds face-node value t of local face f.
 __device__ double entry_E(const SetupArgs& a, const Basis& b, const ElemData& d, int row, int k) {
   const int np = a.mi.np, nfp = a.mi.nfp, dim = a.mi.dim;
@@ -483,7 +588,23 @@ __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
   load_element(a, e, rep, d);
   const int n = a.n_loc, ni = a.n_in, nc = a.ncol;
   double* A = a.scratch + le * (int64_t)n * nc;
-  if (!a.assembled) {
+  const bool sf = !rep && m.dim == 2 && a.pde != kShallowWater;
+  if (sf) {
+    // face terms of L, and E, F, entry by entry; then the volume terms of L
+    // by sum factorisation
+    __shared__ double cq[kMaxSfNq];
+    __shared__ double T[kMaxSfT];
+    for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
+      int r = idx / nc, col = idx % nc;
+      double v;
+      if (col < n) v = entry_L_face(a, b, d, r, col);
+      else if (col < n + ni) v = entry_E(a, b, d, r, col - n);
+      else v = entry_F(a, b, d, r);
+      A[idx] = v;
+    }
+    __syncthreads();
+    assemble_volume_2d(a, b, rt, d, A, nc, cq, T);
+  } else if (!a.assembled) {
     for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) {
       int r = idx / nc, col = idx % nc;
       double v;
