@@ -405,6 +405,16 @@ static ihdg_status setup_impl(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde
   const size_t per = (size_t)sz.n_loc * ncol * 8;
   if (scratch_bytes < per) return IHDG_ERR_NOMEM;
   int64_t chunk = shared ? 1 : std::min<int64_t>(mi.n_el, (int64_t)(scratch_bytes / per));
+  // conv.-diff. with per-element operators: the flux unknowns are condensed
+  // out with constants formed once (at the start of the scratch), and each
+  // element eliminates an np x (np + n_in + 1) system; the constants and one
+  // such system fit wherever one full system does
+  const bool cd_condensed = pde == IHDG_CONVDIFF && !shared && mi.dim == 2;
+  const size_t cst_bytes = cd_condensed ? ihdg::cd_consts_doubles(mi.np, sz.n_in) * 8 : 0;
+  if (cd_condensed) {
+    const size_t per_cd = (size_t)mi.np * (mi.np + sz.n_in + 1) * 8;
+    chunk = std::min<int64_t>(mi.n_el, (int64_t)((scratch_bytes - cst_bytes) / per_cd));
+  }
 
   ihdg_ctx* c = new ihdg_ctx();
   c->hs = new HostStage();
@@ -532,6 +542,11 @@ static ihdg_status setup_impl(const ihdg_mesh* mesh, int32_t order, ihdg_pde pde
     }
   } else {
     a.shared_rep = 0;
+    if (cd_condensed) {
+      a.cst = (double*)scratch;
+      if (ihdg::launch_cd_consts(a, st) != hipSuccess) return bail(IHDG_ERR_HIP, "setup constants");
+      a.scratch = (double*)((char*)scratch + cst_bytes);
+    }
     for (int64_t e0 = 0; e0 < mi.n_el; e0 += chunk) {
       a.e0 = e0;
       a.count = std::min<int64_t>(chunk, mi.n_el - e0);

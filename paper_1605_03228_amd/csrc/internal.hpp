@@ -33,6 +33,7 @@ struct SetupArgs {
   int flux;         // transport: 0 upwind, 1 NPC
   int shared_rep;   // 1: assemble one representative element, all faces treated as interior
   int assembled;    // 1: the augmented matrix is already in scratch (k_setup only eliminates)
+  double* cst;      // conv.-diff. per-element setup: the flux blocks' constants (static condensation), or null
   int64_t e0;       // first element of this chunk
   int64_t count;    // elements in this chunk
   double* scratch;  // count x n_loc x ncol augmented matrices
@@ -104,6 +105,11 @@ constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
 hipError_t noalloc_scratch(hipStream_t s, void** out);
 
 hipError_t launch_setup(const SetupArgs& a, hipStream_t s);
+// Conv.-diff. with per-element operators (2-D): the doubles of the constants
+// of its static condensation, and the kernel that forms them in a.cst (work
+// space: a.G64, which the element setup overwrites afterwards).
+size_t cd_consts_doubles(int np, int n_in);
+hipError_t launch_cd_consts(const SetupArgs& a, hipStream_t s);
 hipError_t launch_shared_c(const SetupArgs& a, hipStream_t s);
 hipError_t launch_maps(const SetupArgs& a, int* fmap, hipStream_t s);
 hipError_t launch_time_operator(const SetupArgs& a, double* H, hipStream_t s);

@@ -332,11 +332,11 @@ __device__ void sf_add_2d(const RefTab& rt, const MeshInfo& m, const double* cq,
 // added to A, term by term as in entry_L: the coefficient of each term at the
 // quadrature points goes to cq (LDS), then sf_add_2d.
 __device__ void assemble_volume_2d(const SetupArgs& a, const Basis& b, const RefTab& rt, const ElemData& d,
-                                   double* A, int nc, double* cq, double* T) {
+                                   double* A, int nc, double* cq, double* T, bool u_only = false, int uoff = -1) {
   const MeshInfo& m = a.mi;
   const int np = m.np, nq = m.nq, dim = 2;
   const Coeffs& c = a.cf;
-  const int uo = a.pde == kTransport ? 0 : dim * np;  // offset of the u block
+  const int uo = uoff >= 0 ? uoff : (a.pde == kTransport ? 0 : dim * np);  // offset of the u block
   // convection: -(u, beta . grad v) per axis, and -(u, (div beta) v) + (sigma or nu) (u, v)
   for (int ax = 0; ax < dim; ++ax) {
     for (int q = threadIdx.x; q < nq; q += blockDim.x) cq[q] = -b.W(q) * d.beta[q][ax];
@@ -347,7 +347,7 @@ __device__ void assemble_volume_2d(const SetupArgs& a, const Basis& b, const Ref
   for (int q = threadIdx.x; q < nq; q += blockDim.x) cq[q] = b.W(q) * (react - d.divb[q]);
   __syncthreads();
   sf_add_2d(rt, m, cq, -1, -1, T, A, nc, uo, uo);
-  if (a.pde == kTransport) return;
+  if (a.pde == kTransport || u_only) return;
   // conv.-diff. flux blocks: (s_a, t_a) / kappa, -(u, d_a t_a), -(s_a, d_a v)
   for (int q = threadIdx.x; q < nq; q += blockDim.x) cq[q] = b.W(q) / c.kappa;
   __syncthreads();
@@ -918,6 +918,203 @@ hipError_t launch_node_points(const MeshInfo& mi, const RefTab& rt, double* x, h
 // them for 2-D p <= 5 and 3-D p = 1 (at 2-D p = 5, 43 KB, two workgroups fit
 // per CU instead of four, and the tables still halve the assembly's work),
 // the values without the derivatives for 2-D p = 6 and 3-D p = 2.
+// ---------------------------------------------------------------------------
+// Convection-diffusion with per-element operators (2-D): static condensation
+// of the flux unknowns.  With fields s_a (a < 2) and u, the local system is
+//   (M / kappa) s_a - S_a u            = E_a x + F_a
+//   sum_a (-S_a + P_a) s_a + D_K u     = E_u x + F_u
+// (M the mass matrix, S_a[i][j] = (l_j, d_a l_i), P_a the face terms of the
+// s_a columns of the u rows, E_a the flux rows' face terms): on the uniform
+// mesh M, S_a, P_a and E_a are the same for every element.  Eliminating s_a,
+//   (D_K + K) u = (E_u - R) x + F_u - sum_a Q_a F_a,
+//   s_a = H_a u + J_a x + kappa M^{-1} F_a,
+// with Q_a = (-S_a + P_a) kappa M^{-1}, K = sum_a Q_a S_a, R = sum_a Q_a E_a,
+// H_a = kappa M^{-1} S_a, J_a = kappa M^{-1} E_a, formed once.  Each element
+// then eliminates an np x (np + n_in + 1) system in place of the
+// 3 np x (3 np + n_in + 1) one.
+//
+// Layout of the constants (doubles): kappa M^{-1} [np^2], Q_0, Q_1 [np^2],
+// K [np^2], H_0, H_1 [np^2], R [np x n_in], J_0, J_1 [np x n_in].
+// ---------------------------------------------------------------------------
+size_t cd_consts_doubles(int np, int n_in) { return (size_t)7 * np * np + (size_t)3 * np * n_in; }
+
+__global__ __launch_bounds__(kST) void k_cd_consts(SetupArgs a) {
+  __shared__ RefTab rt;
+  __shared__ ElemData d;  // not read: the flux rows' entries depend on the geometry only
+  if (threadIdx.x == 0) rt = a.rt;
+  __syncthreads();
+  const MeshInfo& m = a.mi;
+  Basis b(rt, m);
+  const int np = m.np, ni = a.n_in, np2 = np * np;
+  const double kappa = a.cf.kappa;
+  double* cst = a.cst;
+  double* Mk = cst;
+  double* Q = cst + np2;
+  double* K = cst + 3 * np2;
+  double* H = cst + 4 * np2;
+  double* R = cst + 6 * np2;
+  double* J = R + (size_t)np * ni;
+  // work space: [M | I] (np x 2 np), S_0, S_1, P_0, P_1 (np^2 each), E_0, E_1 (np x n_in each)
+  double* W = a.G64;
+  double* S = W + 2 * np2;
+  double* P = S + 2 * np2;
+  double* E = P + 2 * np2;
+  for (int idx = threadIdx.x; idx < np2; idx += blockDim.x) {
+    const int i = idx / np, j = idx % np;
+    W[i * 2 * np + j] = mass(b, i, j);
+    W[i * 2 * np + np + j] = i == j ? 1.0 : 0.0;
+    for (int ax = 0; ax < 2; ++ax) {
+      S[ax * np2 + idx] = stiff(b, ax, i, j);
+      double v = 0.0;
+      for (int f = 0; f < m.nf; ++f)
+        if ((f >> 1) == ax) v += face_sign(f) * face_mass(b, f, i, j, nullptr);
+      P[ax * np2 + idx] = v;
+    }
+  }
+  for (int idx = threadIdx.x; idx < 2 * np * ni; idx += blockDim.x) {
+    const int ax = idx / (np * ni), r = idx % (np * ni);
+    E[idx] = entry_E(a, b, d, ax * np + r / ni, r % ni);
+  }
+  __syncthreads();
+  gauss_jordan(W, np, 2 * np, &a.flags[0]);
+  for (int idx = threadIdx.x; idx < np2; idx += blockDim.x) Mk[idx] = kappa * W[(idx / np) * 2 * np + np + idx % np];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 2 * np2; idx += blockDim.x) {
+    const int ax = idx / np2, i = (idx % np2) / np, j = idx % np;
+    double q = 0.0, h = 0.0;
+    for (int k = 0; k < np; ++k) {
+      q += (P[ax * np2 + i * np + k] - S[ax * np2 + i * np + k]) * Mk[k * np + j];
+      h += Mk[i * np + k] * S[ax * np2 + k * np + j];
+    }
+    Q[idx] = q;
+    H[idx] = h;
+  }
+  for (int idx = threadIdx.x; idx < 2 * np * ni; idx += blockDim.x) {
+    const int ax = idx / (np * ni), i = (idx % (np * ni)) / ni, k = idx % ni;
+    double v = 0.0;
+    for (int j = 0; j < np; ++j) v += Mk[i * np + j] * E[ax * np * ni + j * ni + k];
+    J[idx] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < np2; idx += blockDim.x) {
+    const int i = idx / np, j = idx % np;
+    double v = 0.0;
+    for (int ax = 0; ax < 2; ++ax)
+      for (int k = 0; k < np; ++k) v += Q[ax * np2 + i * np + k] * S[ax * np2 + k * np + j];
+    K[idx] = v;
+  }
+  for (int idx = threadIdx.x; idx < np * ni; idx += blockDim.x) {
+    const int i = idx / ni, k = idx % ni;
+    double v = 0.0;
+    for (int ax = 0; ax < 2; ++ax)
+      for (int j = 0; j < np; ++j) v += Q[ax * np2 + i * np + j] * E[ax * np * ni + j * ni + k];
+    R[idx] = v;
+  }
+}
+
+hipError_t launch_cd_consts(const SetupArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cd_consts, dim3(1), dim3(kST), 0, s, a);
+  return hipGetLastError();
+}
+
+// One element of convection-diffusion with per-element operators: the
+// condensed system on u (face terms entry by entry, volume terms by sum
+// factorisation), its elimination, then the flux rows from the constants.
+template <int kTab>
+__global__ __launch_bounds__(kST) void k_setup_cd(SetupArgs a) {
+  __shared__ RefTab rt;
+  __shared__ ElemData d;
+  __shared__ double cq[kMaxSfNq];
+  __shared__ double T[kMaxSfT];
+  __shared__ double Fs[2 * 49];
+  extern __shared__ double basis_tab[];  // kTab only
+  if (threadIdx.x == 0) rt = a.rt;
+  __syncthreads();
+  const MeshInfo& m = a.mi;
+  const int64_t le = blockIdx.x;
+  const int64_t e = a.e0 + le;
+  if (le >= a.count) return;
+  Basis b(rt, m);
+  if constexpr (kTab > 0) {
+    fill_basis_tab(b, basis_tab, kTab == 2);
+    __syncthreads();
+    b.tab = basis_tab;
+    if constexpr (kTab == 2) b.tabd = basis_tab + m.nq + m.nq * m.np;
+  }
+  load_element(a, e, false, d);
+  const int np = m.np, ni = a.n_in, ns = np + ni + 1, np2 = np * np, n = a.n_loc, uo = 2 * np;
+  const double* cst = a.cst;
+  const double* Mk = cst;
+  const double* Q = cst + np2;
+  const double* K = cst + 3 * np2;
+  const double* H = cst + 4 * np2;
+  const double* R = cst + 6 * np2;
+  const double* J = R + (size_t)np * ni;
+  double* A = a.scratch + le * (int64_t)np * ns;
+  for (int r = threadIdx.x; r < 2 * np; r += blockDim.x) Fs[r] = entry_F(a, b, d, r);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < np * ns; idx += blockDim.x) {
+    const int i = idx / ns, col = idx % ns;
+    double v;
+    if (col < np) {
+      v = entry_L_face(a, b, d, uo + i, uo + col) + K[i * np + col];
+    } else if (col < np + ni) {
+      v = entry_E(a, b, d, uo + i, col - np) - R[i * ni + col - np];
+    } else {
+      v = entry_F(a, b, d, uo + i);
+      for (int ax = 0; ax < 2; ++ax)
+        for (int j = 0; j < np; ++j) v -= Q[ax * np2 + i * np + j] * Fs[ax * np + j];
+    }
+    A[idx] = v;
+  }
+  __syncthreads();
+  assemble_volume_2d(a, b, rt, d, A, ns, cq, T, true, 0);
+  // face projections
+  if (threadIdx.x < m.nf) {
+    const int f = threadIdx.x;
+    double P[3 * 49];
+    cd_projection(a, b, d, f, P);
+    const int np3 = 3 * m.nfp * m.nfp;
+    const int64_t blk = e / kLanes;
+    const int lane = (int)(e % kLanes);
+    for (int k = 0; k < np3; ++k) {
+      const int64_t o = ((blk * m.nf + f) * np3 + k) * kLanes + lane;
+      a.P64[o] = P[k];
+      if (a.P32) a.P32[o] = (float)P[k];
+    }
+  }
+  __syncthreads();
+  gauss_jordan(A, np, ns, &a.flags[0]);
+  const int64_t blk = e / kLanes;
+  const int lane = (int)(e % kLanes);
+  for (int idx = threadIdx.x; idx < n * ni; idx += blockDim.x) {
+    const int r = idx / ni, k = idx % ni;
+    double v;
+    if (r >= uo) {
+      v = A[(int64_t)(r - uo) * ns + np + k];
+    } else {
+      const int ax = r / np, i = r % np;
+      v = J[ax * np * ni + i * ni + k];
+      for (int j = 0; j < np; ++j) v += H[ax * np2 + i * np + j] * A[(int64_t)j * ns + np + k];
+    }
+    const int64_t o = ((blk * n + r) * ni + k) * kLanes + lane;
+    a.G64[o] = v;
+    if (a.G32) a.G32[o] = (float)v;
+  }
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    double v;
+    if (r >= uo) {
+      v = A[(int64_t)(r - uo) * ns + np + ni];
+    } else {
+      const int ax = r / np, i = r % np;
+      v = 0.0;
+      for (int j = 0; j < np; ++j)
+        v += H[ax * np2 + i * np + j] * A[(int64_t)j * ns + np + ni] + Mk[i * np + j] * Fs[ax * np + j];
+    }
+    a.c64[(blk * n + r) * kLanes + lane] = v;
+  }
+}
+
 // The augmented matrix of the representative element of a shared operator,
 // one entry per thread over as many workgroups as it takes (the same entry
 // functions as k_setup, so the same values); k_setup then only eliminates.
@@ -953,6 +1150,15 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   const size_t nq = (size_t)a.mi.nq, np = (size_t)a.mi.np;
   const size_t full = nq * (1 + (size_t)(1 + a.mi.dim) * np) * sizeof(double);
   const size_t wb = nq * (1 + np) * sizeof(double);
+  if (a.cst) {  // conv.-diff., per-element operators, 2-D: condensed on u
+    if (full <= 48 * 1024)
+      hipLaunchKernelGGL(k_setup_cd<2>, dim3((unsigned)a.count), dim3(kST), full, s, a);
+    else if (wb <= 48 * 1024)
+      hipLaunchKernelGGL(k_setup_cd<1>, dim3((unsigned)a.count), dim3(kST), wb, s, a);
+    else
+      hipLaunchKernelGGL(k_setup_cd<0>, dim3((unsigned)a.count), dim3(kST), 0, s, a);
+    return hipGetLastError();
+  }
   if (full <= 48 * 1024)
     hipLaunchKernelGGL(k_setup<2>, dim3((unsigned)a.count), dim3(kST), full, s, a);
   else if (wb <= 48 * 1024)

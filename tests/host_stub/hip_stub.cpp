@@ -196,6 +196,8 @@ static hipError_t fill(double* out, int n, hipStream_t s) {
 }
 
 hipError_t launch_setup(const SetupArgs&, hipStream_t s) { return nop(s); }
+size_t cd_consts_doubles(int np, int n_in) { return (size_t)7 * np * np + (size_t)3 * np * n_in; }
+hipError_t launch_cd_consts(const SetupArgs&, hipStream_t s) { return nop(s); }
 hipError_t launch_shared_c(const SetupArgs&, hipStream_t s) { return nop(s); }
 hipError_t launch_maps(const SetupArgs&, int*, hipStream_t s) { return nop(s); }
 hipError_t launch_time_operator(const SetupArgs&, double*, hipStream_t s) { return nop(s); }
