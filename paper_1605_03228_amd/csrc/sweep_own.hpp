@@ -215,6 +215,21 @@ __device__ __forceinline__ void own_chain(OwnV4<T>* acc, T (*av)[OwnShape<T, P, 
   }
 }
 
+// The same chain with every A operand in registers for the whole kernel (the
+// FP32 kernel: 4 x 23 operands fit beside the block's data at p = 3).
+template <typename T, int P, int MASK, int S>
+__device__ __forceinline__ void own_chain_reg(OwnV4<T>* acc, const T (*ar)[OwnShape<T, P, MASK>::KT],
+                                              const T (*ut)[4], const T* bg,
+                                              const T (*bi)[OwnShape<T, P, MASK>::KF]) {
+  typedef OwnShape<T, P, MASK> Sh;
+  if constexpr (S < Sh::KT) {
+    const T b = own_bop<T, P, MASK, S>(ut, bg, bi);
+#pragma unroll
+    for (int mt = 0; mt < Sh::MT; ++mt) acc[mt] = Mfma<T>::mma(ar[mt][S], b, acc[mt]);
+    own_chain_reg<T, P, MASK, S + 1>(acc, ar, ut, bg, bi);
+  }
+}
+
 template <int P, int MASK>
 __device__ __forceinline__ void own_fmap(const SweepArgs& a, int64_t blk, int le, int (&sin)[3], int (&sout)[3]) {
   typedef OwnShape<double, P, MASK> Sh;
@@ -226,9 +241,10 @@ __device__ __forceinline__ void own_fmap(const SweepArgs& a, int64_t blk, int le
   }
 }
 
-template <typename T, int P, int MASK>
+template <typename T, int P, int MASK, bool AREG = false>
 __device__ __forceinline__ void own_block(const SweepArgs& a, int64_t blk, int wt, const int (&sin)[3],
-                                          const int (&sout)[3], const T* gs, const double* wl, double* red) {
+                                          const int (&sout)[3], const T* gs, const T (*ar)[OwnShape<T, P, MASK>::KT],
+                                          const double* wl, double* red) {
   typedef OwnShape<T, P, MASK> Sh;
   typedef typename Mfma<T>::v4 v4;
   constexpr int MT = Sh::MT, KF = Sh::KF, NLOC = Sh::NLOC, NFP = Sh::NFP, NG = Sh::NG;
@@ -287,12 +303,16 @@ __device__ __forceinline__ void own_block(const SweepArgs& a, int64_t blk, int w
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[mt][r] = T(0);
-  T av[kOwnPrefetch + 1][MT];
+  if constexpr (AREG) {
+    own_chain_reg<T, P, MASK, 0>(acc, ar, ut, bg, bi);
+  } else {
+    T av[kOwnPrefetch + 1][MT];
 #pragma unroll
-  for (int s = 0; s < kOwnPrefetch && s < Sh::KT; ++s)
+    for (int s = 0; s < kOwnPrefetch && s < Sh::KT; ++s)
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) av[s][mt] = gs[(mt * Sh::KT + s) * kLanes + lane];
-  own_chain<T, P, MASK, 0>(acc, av, ut, bg, bi, gs, lane);
+      for (int mt = 0; mt < MT; ++mt) av[s][mt] = gs[(mt * Sh::KT + s) * kLanes + lane];
+    own_chain<T, P, MASK, 0>(acc, av, ut, bg, bi, gs, lane);
+  }
   bool bad = false;
   if (e < a.n_el)
 #pragma unroll
@@ -332,10 +352,10 @@ __device__ __forceinline__ int64_t own_block_index(int64_t n_blk, int64_t i) {
 }
 
 // Waves per SIMD the register budget is cut for (measured best without
-// spills): FP64 2, FP32 3.
+// spills): 2 (FP32: with its A operands in registers).
 template <typename T>
 struct OwnOcc {
-  static constexpr int W = sizeof(T) == 8 ? 2 : 3;
+  static constexpr int W = 2;
 };
 
 // Barrier for the norm partials in LDS: waits for this wave's LDS accesses
@@ -366,12 +386,21 @@ void k_sweep_own(SweepArgs a) {
   int sin[3], sout[3];
   own_fmap<P, MASK>(a, blk, le, sin, sout);
   __syncthreads();
+  // FP32: the wave's A operands stay in registers for the whole kernel
+  constexpr bool AREG = sizeof(T) == 4;
+  T ar[AREG ? Sh::MT : 1][Sh::KT];
+  if constexpr (AREG) {
+#pragma unroll
+    for (int mt = 0; mt < Sh::MT; ++mt)
+#pragma unroll
+      for (int ks = 0; ks < Sh::KT; ++ks) ar[mt][ks] = gs[(mt * Sh::KT + ks) * kLanes + (tid & 63)];
+  }
   for (int64_t i = 1; blk < a.n_blk; ++i) {
     const int64_t nxt = own_block_index(a.n_blk, i);
     int nsin[3], nsout[3];
     own_fmap<P, MASK>(a, nxt, le, nsin, nsout);
     double* rb = red[i & 1];
-    own_block<T, P, MASK>(a, blk, wt, sin, sout, gs, wl, rb);
+    own_block<T, P, MASK, AREG>(a, blk, wt, sin, sout, gs, ar, wl, rb);
     own_lds_barrier();
     if (tid == 0) {
       a.partials[2 * blk] = (rb[0] + rb[1]) + (rb[2] + rb[3]);
@@ -395,7 +424,7 @@ __device__ __forceinline__ void own_batched_body(const SweepArgs& a, int64_t blk
   int sin[3], sout[3];
   own_fmap<P, MASK>(a, blk, wt * 16 + (tid & 15), sin, sout);
   __syncthreads();
-  own_block<T, P, MASK>(a, blk, wt, sin, sout, gs, wl, red);
+  own_block<T, P, MASK>(a, blk, wt, sin, sout, gs, nullptr, wl, red);
   __syncthreads();
   if (tid == 0) {
     a.partials[2 * blk] = (red[0] + red[1]) + (red[2] + red[3]);
