@@ -34,6 +34,7 @@ struct SetupArgs {
   int shared_rep;   // 1: assemble one representative element, all faces treated as interior
   int assembled;    // 1: the augmented matrix is already in scratch (k_setup only eliminates)
   double* cst;      // conv.-diff. per-element setup: the flux blocks' constants (static condensation), or null
+  int gj_lds;       // 1: the elimination runs on a copy of the matrix in dynamic LDS (set by launch_setup)
   int64_t e0;       // first element of this chunk
   int64_t count;    // elements in this chunk
   double* scratch;  // count x n_loc x ncol augmented matrices

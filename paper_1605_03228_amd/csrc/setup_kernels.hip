@@ -10,6 +10,7 @@
 //
 // One workgroup handles one element; the augmented matrix lives in global
 // scratch (at most 147 x 176 doubles per element).
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -494,74 +495,104 @@ __device__ void gauss_jordan(double* A, int n, int ncol, int* flag) {
   }
 }
 
-// Conv.-diff. face projection of local face f: P = M_alpha^{-1} [M | M_{(alpha+bn)/2} | M_{(alpha-bn)/2}]
-// (nfp x 3 nfp, row-major), the weak form of the trace of the conservation condition.
-__device__ void cd_projection(const SetupArgs& a, const Basis& b, const ElemData& d, int f, double* out) {
-  const int nfp = a.mi.nfp, dim = a.mi.dim;
-  double Ma[49];     // conv.-diff. is 2-D: nfp <= 7
-  double R[7 * 21];
-  for (int cc = 0; cc < nfp; ++cc) {
-    int ic = fnode(a.mi.n1, dim, f, cc);
-    for (int bb = 0; bb < nfp; ++bb) {
-      int ib = fnode(a.mi.n1, dim, f, bb);
-      double m0 = 0, ma = 0, mp = 0, mm = 0;
-      for (int qf = 0; qf < a.mi.nfq; ++qf) {
-        double bn = d.bn[f][qf];
-        double w = b.Wf(f, qf) * b.Bf(f, qf, ib) * b.Bf(f, qf, ic);
-        m0 += w;
-        if (a.cf.tau_star > 0) {  // tau- = tau+ = tau*: weights tau* +- bn over 2 tau*
-          const double ts = a.cf.tau_star;
-          ma += w * 2.0 * ts;
-          mm += w * (ts + bn);
-          mp += w * (ts - bn);
-        } else {                  // upwind: alpha and (alpha +- bn)/2
-          const double al = sqrt(bn * bn + 4.0);
-          ma += w * al;
-          mm += w * 0.5 * (al + bn);
-          mp += w * 0.5 * (al - bn);
+
+// Conv.-diff. face projections P_f = M_alpha^{-1} [M | M_(alpha+bn)/2 |
+// M_(alpha-bn)/2] (nfp x 3 nfp per face), the weak form of the trace of the
+// conservation condition, for all faces of one element at once: wave w takes faces w, w + 4, ...; its lanes form the
+// entries of [M_alpha | M | M_(alpha+bn)/2 | M_(alpha-bn)/2] in LDS and reduce
+// it by Gauss-Jordan with partial pivoting, lane j owning column j; the
+// reduced right-hand blocks are P.  Written to P64/P32 in the per-element
+// layout, or in the shared layout when rep.  Every thread of the workgroup
+// must call it (it synchronises).
+constexpr int kMaxNfp = 7;
+__device__ void cd_projections_all(const SetupArgs& a, const Basis& b, const ElemData& d, int64_t e, bool rep) {
+  __shared__ double ws[4][kMaxNfp * 4 * kMaxNfp];
+  __shared__ int pivs[4];
+  const MeshInfo& m = a.mi;
+  const int nfp = m.nfp, nc4 = 4 * nfp, dim = m.dim;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int np3 = 3 * nfp * nfp;
+  for (int f0 = 0; f0 < m.nf; f0 += 4) {
+    const int f = f0 + w;
+    const bool act = f < m.nf;
+    double* W = ws[w];
+    if (act) {
+      for (int idx = lane; idx < nfp * nfp; idx += 64) {
+        const int cc = idx / nfp, bb = idx % nfp;
+        const int ic = fnode(m.n1, dim, f, cc), ib = fnode(m.n1, dim, f, bb);
+        double m0 = 0, ma = 0, mp = 0, mm = 0;
+        for (int qf = 0; qf < m.nfq; ++qf) {
+          const double bn = d.bn[f][qf];
+          const double wq = b.Wf(f, qf) * b.Bf(f, qf, ib) * b.Bf(f, qf, ic);
+          m0 += wq;
+          if (a.cf.tau_star > 0) {
+            const double ts = a.cf.tau_star;
+            ma += wq * 2.0 * ts;
+            mm += wq * (ts + bn);
+            mp += wq * (ts - bn);
+          } else {
+            const double al = sqrt(bn * bn + 4.0);
+            ma += wq * al;
+            mm += wq * 0.5 * (al + bn);
+            mp += wq * 0.5 * (al - bn);
+          }
+        }
+        W[cc * nc4 + bb] = ma;
+        W[cc * nc4 + nfp + bb] = m0;
+        W[cc * nc4 + 2 * nfp + bb] = mm;
+        W[cc * nc4 + 3 * nfp + bb] = mp;
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < nfp; ++k) {
+      if (act && lane == 0) {
+        int best = k;
+        for (int i = k + 1; i < nfp; ++i)
+          if (fabs(W[i * nc4 + k]) > fabs(W[best * nc4 + k])) best = i;
+        pivs[w] = best;
+      }
+      __syncthreads();
+      const int best = act ? pivs[w] : k;
+      double colk[kMaxNfp];
+      double rk = 0.0;
+      if (act && lane < nc4) {
+        if (best != k) {
+          const double t = W[k * nc4 + lane];
+          W[k * nc4 + lane] = W[best * nc4 + lane];
+          W[best * nc4 + lane] = t;
         }
       }
-      Ma[cc * nfp + bb] = ma;
-      R[cc * 3 * nfp + bb] = m0;
-      R[cc * 3 * nfp + nfp + bb] = mm;
-      R[cc * 3 * nfp + 2 * nfp + bb] = mp;
-    }
-  }
-  // solve Ma X = R (Gaussian elimination with partial pivoting, 3 nfp right-hand sides)
-  const int nr = 3 * nfp;
-  for (int k = 0; k < nfp; ++k) {
-    int best = k;
-    for (int i = k + 1; i < nfp; ++i)
-      if (fabs(Ma[i * nfp + k]) > fabs(Ma[best * nfp + k])) best = i;
-    if (best != k) {
-      for (int j = 0; j < nfp; ++j) {
-        double t = Ma[k * nfp + j];
-        Ma[k * nfp + j] = Ma[best * nfp + j];
-        Ma[best * nfp + j] = t;
+      __syncthreads();
+      if (act && lane < nc4) {
+        const double inv = 1.0 / W[k * nc4 + k];
+        for (int i = 0; i < nfp; ++i) colk[i] = W[i * nc4 + k] * inv;
+        rk = W[k * nc4 + lane];
       }
-      for (int j = 0; j < nr; ++j) {
-        double t = R[k * nr + j];
-        R[k * nr + j] = R[best * nr + j];
-        R[best * nr + j] = t;
+      __syncthreads();
+      if (act && lane < nc4) {
+        for (int i = 0; i < nfp; ++i)
+          if (i != k) W[i * nc4 + lane] -= colk[i] * rk;
+      }
+      __syncthreads();
+    }
+    if (act) {
+      const int64_t blk = e / kLanes;
+      const int el = (int)(e % kLanes);
+      for (int k = lane; k < np3; k += 64) {
+        const int sidx = k / (nfp * nfp), cc = (k / nfp) % nfp, bb = k % nfp;
+        const double v = W[cc * nc4 + (1 + sidx) * nfp + bb] / W[cc * nc4 + cc];
+        if (rep) {
+          a.P64[f * np3 + k] = v;
+          a.P32[f * np3 + k] = (float)v;
+        } else {
+          const int64_t o = ((blk * m.nf + f) * np3 + k) * kLanes + el;
+          a.P64[o] = v;
+          if (a.P32) a.P32[o] = (float)v;
+        }
       }
     }
-    double inv = 1.0 / Ma[k * nfp + k];
-    for (int i = 0; i < nfp; ++i) {
-      if (i == k) continue;
-      double fct = Ma[i * nfp + k] * inv;
-      if (fct == 0.0) continue;
-      for (int j = k; j < nfp; ++j) Ma[i * nfp + j] -= fct * Ma[k * nfp + j];
-      for (int j = 0; j < nr; ++j) R[i * nr + j] -= fct * R[k * nr + j];
-    }
+    __syncthreads();
   }
-  for (int i = 0; i < nfp; ++i) {
-    double inv = 1.0 / Ma[i * nfp + i];
-    for (int j = 0; j < nr; ++j) R[i * nr + j] *= inv;
-  }
-  // out layout: [3][nfp][nfp]: block s, row c, col b
-  for (int s = 0; s < 3; ++s)
-    for (int cc = 0; cc < nfp; ++cc)
-      for (int bb = 0; bb < nfp; ++bb) out[(s * nfp + cc) * nfp + bb] = R[cc * nr + s * nfp + bb];
 }
 
 // kTab: 2 = W, B and D come from tables in dynamic LDS, 1 = W and B only, 0 =
@@ -616,49 +647,40 @@ __global__ __launch_bounds__(kST) void k_setup(SetupArgs a) {
     }
   }
   // conv.-diff. face projections
-  if (a.pde == kConvDiff && threadIdx.x < m.nf) {
-    const int f = threadIdx.x;
-    double P[3 * 49];
-    cd_projection(a, b, d, f, P);
-    const int np3 = 3 * m.nfp * m.nfp;
-    const int64_t blk = e / kLanes;
-    const int lane = (int)(e % kLanes);
-    for (int k = 0; k < np3; ++k) {
-      if (rep) {
-        a.P64[f * np3 + k] = P[k];
-        a.P32[f * np3 + k] = (float)P[k];
-      } else {
-        int64_t o = ((blk * m.nf + f) * np3 + k) * kLanes + lane;
-        a.P64[o] = P[k];
-        if (a.P32) a.P32[o] = (float)P[k];
-      }
-    }
-  }
+  if (a.pde == kConvDiff) cd_projections_all(a, b, d, e, rep);
   __syncthreads();
-  gauss_jordan(A, n, nc, &a.flags[0]);
+  // the elimination on a copy in LDS where it fits (the basis tables are no
+  // longer needed): each pivot step's reads and writes then stay on the CU
+  double* Ag = A;
+  if (a.gj_lds) {
+    for (int idx = threadIdx.x; idx < n * nc; idx += blockDim.x) basis_tab[idx] = A[idx];
+    __syncthreads();
+    Ag = basis_tab;
+  }
+  gauss_jordan(Ag, n, nc, &a.flags[0]);
   // outputs
   if (rep) {
     for (int idx = threadIdx.x; idx < n * ni; idx += blockDim.x) {
       int r = idx / ni, j = idx % ni;
-      double v = A[(int64_t)r * nc + n + j];
+      double v = Ag[(int64_t)r * nc + n + j];
       a.G64[idx] = v;
       a.G32[idx] = (float)v;
     }
     for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
       int r = idx / n, j = idx % n;
-      a.Linv[idx] = A[(int64_t)r * nc + n + ni + j];
+      a.Linv[idx] = Ag[(int64_t)r * nc + n + ni + j];
     }
   } else {
     const int64_t blk = e / kLanes;
     const int lane = (int)(e % kLanes);
     for (int idx = threadIdx.x; idx < n * ni; idx += blockDim.x) {
       int r = idx / ni, j = idx % ni;
-      double v = A[(int64_t)r * nc + n + j];
+      double v = Ag[(int64_t)r * nc + n + j];
       int64_t o = ((blk * n + r) * ni + j) * kLanes + lane;
       a.G64[o] = v;
       if (a.G32) a.G32[o] = (float)v;
     }
-    for (int r = threadIdx.x; r < n; r += blockDim.x) a.c64[(blk * n + r) * kLanes + lane] = A[(int64_t)r * nc + n + ni];
+    for (int r = threadIdx.x; r < n; r += blockDim.x) a.c64[(blk * n + r) * kLanes + lane] = Ag[(int64_t)r * nc + n + ni];
   }
 }
 
@@ -1070,32 +1092,26 @@ __global__ __launch_bounds__(kST) void k_setup_cd(SetupArgs a) {
   __syncthreads();
   assemble_volume_2d(a, b, rt, d, A, ns, cq, T, true, 0);
   // face projections
-  if (threadIdx.x < m.nf) {
-    const int f = threadIdx.x;
-    double P[3 * 49];
-    cd_projection(a, b, d, f, P);
-    const int np3 = 3 * m.nfp * m.nfp;
-    const int64_t blk = e / kLanes;
-    const int lane = (int)(e % kLanes);
-    for (int k = 0; k < np3; ++k) {
-      const int64_t o = ((blk * m.nf + f) * np3 + k) * kLanes + lane;
-      a.P64[o] = P[k];
-      if (a.P32) a.P32[o] = (float)P[k];
-    }
-  }
+  cd_projections_all(a, b, d, e, false);
   __syncthreads();
-  gauss_jordan(A, np, ns, &a.flags[0]);
+  double* Ag = A;  // the elimination on a copy in LDS where it fits, as in k_setup
+  if (a.gj_lds) {
+    for (int idx = threadIdx.x; idx < np * ns; idx += blockDim.x) basis_tab[idx] = A[idx];
+    __syncthreads();
+    Ag = basis_tab;
+  }
+  gauss_jordan(Ag, np, ns, &a.flags[0]);
   const int64_t blk = e / kLanes;
   const int lane = (int)(e % kLanes);
   for (int idx = threadIdx.x; idx < n * ni; idx += blockDim.x) {
     const int r = idx / ni, k = idx % ni;
     double v;
     if (r >= uo) {
-      v = A[(int64_t)(r - uo) * ns + np + k];
+      v = Ag[(int64_t)(r - uo) * ns + np + k];
     } else {
       const int ax = r / np, i = r % np;
       v = J[ax * np * ni + i * ni + k];
-      for (int j = 0; j < np; ++j) v += H[ax * np2 + i * np + j] * A[(int64_t)j * ns + np + k];
+      for (int j = 0; j < np; ++j) v += H[ax * np2 + i * np + j] * Ag[(int64_t)j * ns + np + k];
     }
     const int64_t o = ((blk * n + r) * ni + k) * kLanes + lane;
     a.G64[o] = v;
@@ -1104,12 +1120,12 @@ __global__ __launch_bounds__(kST) void k_setup_cd(SetupArgs a) {
   for (int r = threadIdx.x; r < n; r += blockDim.x) {
     double v;
     if (r >= uo) {
-      v = A[(int64_t)(r - uo) * ns + np + ni];
+      v = Ag[(int64_t)(r - uo) * ns + np + ni];
     } else {
       const int ax = r / np, i = r % np;
       v = 0.0;
       for (int j = 0; j < np; ++j)
-        v += H[ax * np2 + i * np + j] * A[(int64_t)j * ns + np + ni] + Mk[i * np + j] * Fs[ax * np + j];
+        v += H[ax * np2 + i * np + j] * Ag[(int64_t)j * ns + np + ni] + Mk[i * np + j] * Fs[ax * np + j];
     }
     a.c64[(blk * n + r) * kLanes + lane] = v;
   }
@@ -1150,21 +1166,22 @@ hipError_t launch_setup(const SetupArgs& a, hipStream_t s) {
   const size_t nq = (size_t)a.mi.nq, np = (size_t)a.mi.np;
   const size_t full = nq * (1 + (size_t)(1 + a.mi.dim) * np) * sizeof(double);
   const size_t wb = nq * (1 + np) * sizeof(double);
+  const int kt = full <= 48 * 1024 ? 2 : (wb <= 48 * 1024 ? 1 : 0);
+  const size_t tab = kt == 2 ? full : (kt == 1 ? wb : 0);
+  // the matrix the element eliminates: condensed (conv.-diff.) or full
+  const size_t mat = a.cst ? np * (np + (size_t)a.n_in + 1) * sizeof(double) : (size_t)a.n_loc * a.ncol * sizeof(double);
+  SetupArgs b = a;
+  b.gj_lds = mat <= 48 * 1024 ? 1 : 0;
+  const size_t dyn = std::max(tab, b.gj_lds ? mat : (size_t)0);
   if (a.cst) {  // conv.-diff., per-element operators, 2-D: condensed on u
-    if (full <= 48 * 1024)
-      hipLaunchKernelGGL(k_setup_cd<2>, dim3((unsigned)a.count), dim3(kST), full, s, a);
-    else if (wb <= 48 * 1024)
-      hipLaunchKernelGGL(k_setup_cd<1>, dim3((unsigned)a.count), dim3(kST), wb, s, a);
-    else
-      hipLaunchKernelGGL(k_setup_cd<0>, dim3((unsigned)a.count), dim3(kST), 0, s, a);
+    if (kt == 2) hipLaunchKernelGGL(k_setup_cd<2>, dim3((unsigned)a.count), dim3(kST), dyn, s, b);
+    else if (kt == 1) hipLaunchKernelGGL(k_setup_cd<1>, dim3((unsigned)a.count), dim3(kST), dyn, s, b);
+    else hipLaunchKernelGGL(k_setup_cd<0>, dim3((unsigned)a.count), dim3(kST), dyn, s, b);
     return hipGetLastError();
   }
-  if (full <= 48 * 1024)
-    hipLaunchKernelGGL(k_setup<2>, dim3((unsigned)a.count), dim3(kST), full, s, a);
-  else if (wb <= 48 * 1024)
-    hipLaunchKernelGGL(k_setup<1>, dim3((unsigned)a.count), dim3(kST), wb, s, a);
-  else
-    hipLaunchKernelGGL(k_setup<0>, dim3((unsigned)a.count), dim3(kST), 0, s, a);
+  if (kt == 2) hipLaunchKernelGGL(k_setup<2>, dim3((unsigned)a.count), dim3(kST), dyn, s, b);
+  else if (kt == 1) hipLaunchKernelGGL(k_setup<1>, dim3((unsigned)a.count), dim3(kST), dyn, s, b);
+  else hipLaunchKernelGGL(k_setup<0>, dim3((unsigned)a.count), dim3(kST), dyn, s, b);
   return hipGetLastError();
 }
 
