@@ -733,7 +733,7 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best, bool timed) {
   // other work on the GPU (a serving loop's batch and Krylov workers) slows
   // whichever candidate it overlaps, and the minimum over interleaved rounds
   // is the least disturbed estimate of each.
-  const int reps = nb >= 256 ? 5 : 20;
+  const int reps = nb >= 256 ? 2 : 7;  // per round
   constexpr int kRounds = 3;
   std::vector<float> bt(cand.size(), 1e30f);
   for (int round = 0; round < kRounds; ++round) {

@@ -369,16 +369,18 @@ __device__ double entry_E(const SetupArgs& a, const Basis& b, const ElemData& d,
   const int nj = fnode(a.mi.n1, dim, f, t);
   if (!b.on_face(f, ni)) return 0.0;
   const Coeffs& c = a.cf;
-  double w[kMaxNfq];
+  // the face-weighted products of face_mass, the weight formed point by
+  // point (no per-point array: it would live in scratch memory)
   if (a.pde == kTransport) {
     // upwind: weighted trace |beta.n| uhat (own trace on outflow, neighbour's on inflow);
     // on a boundary face only the outflow part.  NPC: tau uhat, nonzero on inflow only.
+    double v = 0.0;
     for (int qf = 0; qf < a.mi.nfq; ++qf) {
-      double bn = d.bn[f][qf];
-      if (a.flux == 1) w[qf] = d.interior[f] ? fmax(-bn, 0.0) : 0.0;
-      else w[qf] = d.interior[f] ? fabs(bn) : fmax(bn, 0.0);
+      const double bn = d.bn[f][qf];
+      const double w = a.flux == 1 ? (d.interior[f] ? fmax(-bn, 0.0) : 0.0) : (d.interior[f] ? fabs(bn) : fmax(bn, 0.0));
+      v += b.Wf(f, qf) * w * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
     }
-    return face_mass(b, f, ni, nj, w);
+    return v;
   }
   if (a.pde == kShallowWater) {
     double fm = face_mass(b, f, ni, nj, nullptr);
@@ -386,8 +388,10 @@ __device__ double entry_E(const SetupArgs& a, const Basis& b, const ElemData& d,
     return (fi - 1 == ax) ? -c.Phi * face_sign(f) * fm : 0.0;
   }
   if (fi < dim) return (fi == ax) ? -face_sign(f) * face_mass(b, f, ni, nj, nullptr) : 0.0;
-  for (int qf = 0; qf < a.mi.nfq; ++qf) w[qf] = tau_cd(d.bn[f][qf], c.tau_star);
-  return face_mass(b, f, ni, nj, w);
+  double v = 0.0;
+  for (int qf = 0; qf < a.mi.nfq; ++qf)
+    v += b.Wf(f, qf) * tau_cd(d.bn[f][qf], c.tau_star) * b.Bf(f, qf, nj) * b.Bf(f, qf, ni);
+  return v;
 }
 
 __device__ double entry_F(const SetupArgs& a, const Basis& b, const ElemData& d, int row) {
