@@ -17,9 +17,9 @@
 // element l % 16) has the layout of a 16-row accumulator tile (FP64: lane l
 // holds rows 4 r + l / 16; FP32: rows 4 (l / 16) + r), so the registers that
 // hold u^k for the increment are the B operands.  Compared with the direct
-// variant (launch shape 5) each own trace is read once, the loads per block
-// fall by a sixth and their registers by a third, which lets a wave keep all
-// of a block's loads in flight at once:
+// variant (launch shape 5) each own trace is read once, a wave issues 54
+// loads per block instead of 62, and the B operands take a third fewer
+// registers:
 //
 //  * K slices of the tile that hold no outflow node are skipped; the axis
 //    whose outflow nodes fall into every slice (x in FP64, y in FP32) is
@@ -29,7 +29,7 @@
 //    4 face nodes per K slice, as in the direct variant;
 //  * the A operands (the combined own-tile operator, the gathered face's and
 //    the inflow faces' columns of G) are formed once per workgroup in LDS, in
-//    the MFMA register order;
+//    the MFMA register order; the FP32 kernel then keeps them in registers;
 //  * persistent, each XCD sweeping a contiguous range of blocks so that the
 //    y- and z-neighbours' traces are read from its own L2.
 //
