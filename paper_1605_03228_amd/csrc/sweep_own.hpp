@@ -30,8 +30,8 @@
 //  * the A operands (the combined own-tile operator, the gathered face's and
 //    the inflow faces' columns of G) are formed once per workgroup in LDS, in
 //    the MFMA register order; the FP32 kernel then keeps them in registers;
-//  * persistent, each XCD sweeping a contiguous range of blocks so that the
-//    y- and z-neighbours' traces are read from its own L2.
+//  * persistent: each workgroup forms the operator once and sweeps its share
+//    of the blocks.
 //
 // The outflow side of every axis is a template parameter (MASK, bit a: the
 // outflow face of axis a is its high face), set from the sign of beta.  Each
@@ -339,16 +339,12 @@ __device__ __forceinline__ void own_block(const SweepArgs& a, int64_t blk, int w
   }
 }
 
-// Block i of this workgroup: XCD x = blockIdx % 8 sweeps the contiguous range
-// [x R, (x + 1) R) of the blocks with its workgroups in turn; n_blk past the end.
+// Block i of this workgroup: the blocks are dealt to the workgroups in turn
+// (n_blk past the end).  Giving each XCD a contiguous range of blocks, so that
+// the y- and z-neighbours' traces would stay in its L2, measured 5% slower.
 __device__ __forceinline__ int64_t own_block_index(int64_t n_blk, int64_t i) {
-  const int64_t g = gridDim.x;
-  const int64_t x = blockIdx.x % kXcds, j = blockIdx.x / kXcds;
-  const int64_t nx = (g - x + kXcds - 1) / kXcds;  // workgroups on this XCD
-  const int64_t R = (n_blk + kXcds - 1) / kXcds;
-  const int64_t lo = x * R, hi = lo + R < n_blk ? lo + R : n_blk;
-  const int64_t b = lo + j + i * nx;
-  return b < hi ? b : n_blk;
+  const int64_t b = blockIdx.x + i * (int64_t)gridDim.x;
+  return b < n_blk ? b : n_blk;
 }
 
 // Waves per SIMD the register budget is cut for (measured best without
