@@ -726,14 +726,19 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best, bool timed) {
   if (e != hipSuccess) return e;
   e = hipEventCreate(&e1);
   if (e != hipSuccess) return e;
-  const void* uin = fp32 ? (const void*)c->dl32[0] : (const void*)c->u64[c->cur];
-  void* uout = fp32 ? (void*)c->dl32[1] : (void*)c->tmp64;
+  // two scratch iterates that the sweeps ping-pong between as in a solve
+  // (zero at setup; zeroed again afterwards): FP64 the spare iterate and the
+  // temporary, never the current iterate; FP32 the correction buffers
+  void* sbuf[2] = {fp32 ? (void*)c->dl32[0] : (void*)c->tmp64, fp32 ? (void*)c->dl32[1] : (void*)c->u64[c->cur ^ 1]};
+  const void* uin = sbuf[0];
+  void* uout = sbuf[1];
   const void* cv = fp32 ? (const void*)c->d32 : (const void*)c->c64;
   // Rounds over the candidates in turn, each candidate's best round kept:
   // other work on the GPU (a serving loop's batch and Krylov workers) slows
   // whichever candidate it overlaps, and the minimum over interleaved rounds
   // is the least disturbed estimate of each.
-  const int reps = nb >= 256 ? 2 : 7;  // per round
+  // sweeps per candidate and round: about 4096 blocks' worth, 2 to 16
+  const int reps = (int)std::max<int64_t>(2, std::min<int64_t>(16, 4096 / std::max<int64_t>(nb, 1)));
   constexpr int kRounds = 3;
   std::vector<float> bt(cand.size(), 1e30f);
   for (int round = 0; round < kRounds; ++round) {
@@ -758,9 +763,17 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best, bool timed) {
               hipSuccess)
             return e;
       if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) return e;
-      for (int i = 0; i < reps; ++i)
-        if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, a, c->stream)) != hipSuccess)
+      for (int i = 0; i < reps; ++i) {
+        // ping-pong between the two buffers, as the sweeps of a solve do
+        SweepArgs ai = a;
+        if (i & 1) {
+          ai.uin = uout;
+          ai.uout = (void*)uin;
+        }
+        if ((e = ihdg::launch_sweep((int)c->pde, c->mi.dim, c->mi.p, fp32, c->shared, w, ai, c->stream)) !=
+            hipSuccess)
           return e;
+      }
       if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) return e;
       if ((e = hipEventSynchronize(e1)) != hipSuccess) return e;
       float ms = 0;
@@ -775,6 +788,11 @@ static hipError_t tune_one(ihdg_ctx* c, bool fp32, int* best, bool timed) {
       bestt = bt[ci];
       bw = cand[ci];
     }
+  for (int k = 0; k < 2; ++k) {
+    e = fp32 ? ihdg::launch_fill_zero_f32((float*)sbuf[k], c->nvec, c->stream)
+             : ihdg::launch_fill_zero_f64((double*)sbuf[k], c->nvec, c->stream);
+    if (e != hipSuccess) return e;
+  }
   *best = bw;
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tuned[key] = bw;
