@@ -15,6 +15,8 @@
 //
 // Usage: harness [threads]   (exit status 0: every run returned a status
 // and no sanitizer fired; ASan aborts the process otherwise)
+//        harness tune        (the autotuner's buffer use, below)
+#include <algorithm>
 #include <atomic>
 #include <functional>
 #include <cstdio>
@@ -225,9 +227,62 @@ void worker(int tid) {
   }
 }
 
+// The autotuner at setup times its candidate launches on two scratch
+// iterates per precision: each launch reads one and writes the other, both
+// are zeroed after the last one, and neither is the iterate a solve starts
+// from.
+int tune_check() {
+  hipStream_t st = (hipStream_t)(uintptr_t)0x2000;
+  DevMem dm;
+  stub_set_fail_at(-1);
+  ihdg_ctx* c = nullptr;
+  stub_record(true);
+  const bool ok = run_ctx(make(0, false, 1, 0, 0, false, false), st, dm, &c, [](ihdg_ctx*) { return true; });
+  const std::vector<StubRec> tune = stub_records();
+  if (!ok || !c) {
+    std::printf("tune: setup failed\n");
+    return 1;
+  }
+  stub_record(true);
+  ihdg_status s = ihdg_sweep(c, 1, nullptr);
+  const std::vector<StubRec> first = stub_records();
+  stub_record(false);
+  stub_drain(st);
+  int bad = 0;
+  if (s != IHDG_OK || first.empty() || first[0].kind != 0) {
+    std::printf("tune: no sweep recorded after setup\n");
+    bad = 1;
+  }
+  for (int fp32 = 0; fp32 < 2 && !bad; ++fp32) {
+    std::vector<const void*> bufs;
+    size_t last = 0, n = 0;
+    for (size_t i = 0; i < tune.size(); ++i) {
+      const StubRec& r = tune[i];
+      if (r.kind != 0 || r.fp32 != (fp32 == 1)) continue;
+      ++n;
+      last = i;
+      for (const void* b : {r.in, r.out})
+        if (std::find(bufs.begin(), bufs.end(), b) == bufs.end()) bufs.push_back(b);
+      if (r.in == r.out) bad = 1;
+    }
+    bool zeroed[2] = {false, false};
+    for (size_t i = last + 1; i < tune.size() && bufs.size() == 2; ++i)
+      for (int k = 0; k < 2; ++k)
+        if (tune[i].kind == 1 && tune[i].out == bufs[k]) zeroed[k] = true;
+    const bool cur_untouched = fp32 || std::find(bufs.begin(), bufs.end(), first[0].in) == bufs.end();
+    std::printf("tune: %s %zu launches on %zu buffers, zeroed %d %d, current iterate untouched %d\n",
+                fp32 ? "fp32" : "fp64", n, bufs.size(), (int)zeroed[0], (int)zeroed[1], (int)cur_untouched);
+    if (n < 4 || bufs.size() != 2 || !zeroed[0] || !zeroed[1] || !cur_untouched) bad = 1;
+  }
+  ihdg_destroy(c);
+  std::printf(bad ? "tune: FAILED\n" : "tune ok\n");
+  return bad;
+}
+
 }  // namespace
 
 int main(int argc, char** argv) {
+  if (argc > 1 && std::strcmp(argv[1], "tune") == 0) return tune_check();
   const int nt = argc > 1 ? std::atoi(argv[1]) : 4;
   std::vector<std::thread> th;
   for (int t = 0; t < nt; ++t) th.emplace_back(worker, t);

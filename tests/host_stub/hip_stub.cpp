@@ -73,7 +73,20 @@ double next_norm() {
   return g_decay;
 }
 
+thread_local bool g_rec = false;
+thread_local std::vector<StubRec> g_recs;
+
+void rec(int kind, bool fp32, const void* in, const void* out) {
+  if (g_rec) g_recs.push_back({kind, fp32, in, out});
+}
+
 }  // namespace
+
+void stub_record(bool on) {
+  g_rec = on;
+  if (on) g_recs.clear();
+}
+std::vector<StubRec> stub_records() { return g_recs; }
 
 struct ihipEvent_t {
   hipStream_t s;
@@ -207,9 +220,18 @@ hipError_t launch_time_rhs(double*, const double*, const double*, const double*,
 }
 hipError_t launch_node_points(const MeshInfo&, const RefTab&, double*, hipStream_t s) { return nop(s); }
 hipError_t launch_quad_points(const MeshInfo&, const RefTab&, double*, double*, hipStream_t s) { return nop(s); }
-hipError_t launch_sweep_transport(int, int, bool, bool, int, const SweepArgs&, hipStream_t s) { return nop(s); }
-hipError_t launch_sweep_sw(int, bool, bool, int, const SweepArgs&, hipStream_t s) { return nop(s); }
-hipError_t launch_sweep_cd(int, bool, bool, int, const SweepArgs&, hipStream_t s) { return nop(s); }
+hipError_t launch_sweep_transport(int, int, bool fp32, bool, int, const SweepArgs& a, hipStream_t s) {
+  rec(0, fp32, a.uin, a.uout);
+  return nop(s);
+}
+hipError_t launch_sweep_sw(int, bool fp32, bool, int, const SweepArgs& a, hipStream_t s) {
+  rec(0, fp32, a.uin, a.uout);
+  return nop(s);
+}
+hipError_t launch_sweep_cd(int, bool fp32, bool, int, const SweepArgs& a, hipStream_t s) {
+  rec(0, fp32, a.uin, a.uout);
+  return nop(s);
+}
 bool direct_supported(int, int) { return true; }
 bool gemm_supported(int, int) { return true; }
 bool own_supported(int, int) { return true; }
@@ -242,8 +264,14 @@ hipError_t launch_reduce_partials(const double*, int64_t, double* out2, hipStrea
 }
 hipError_t launch_diff_to_f32(const double*, const double*, float*, int64_t, hipStream_t s) { return nop(s); }
 hipError_t launch_add_f32_to_f64(double*, const float*, int64_t, hipStream_t s) { return nop(s); }
-hipError_t launch_fill_zero_f32(float*, int64_t, hipStream_t s) { return nop(s); }
-hipError_t launch_fill_zero_f64(double*, int64_t, hipStream_t s) { return nop(s); }
+hipError_t launch_fill_zero_f32(float* p, int64_t, hipStream_t s) {
+  rec(1, true, nullptr, p);
+  return nop(s);
+}
+hipError_t launch_fill_zero_f64(double* p, int64_t, hipStream_t s) {
+  rec(1, false, nullptr, p);
+  return nop(s);
+}
 hipError_t launch_to_user(const double*, double*, int64_t, int, hipStream_t s) { return nop(s); }
 hipError_t launch_from_user(const double*, double*, int64_t, int, hipStream_t s) { return nop(s); }
 hipError_t launch_axpby(double*, double, const double*, double, int64_t, hipStream_t s) { return nop(s); }

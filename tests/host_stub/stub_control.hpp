@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 // Make the n-th stub call of the calling thread fail (n < 1: never) and reset
 // the thread's call count.
@@ -15,3 +16,14 @@ long stub_failed_at();
 // complete after the caller has moved on).
 void stub_drain(hipStream_t s);
 size_t stub_pending(hipStream_t s);
+
+// Sweep launches (kind 0: the iterate read and written, FP32 or not) and zero
+// fills (kind 1: the buffer) of the calling thread, recorded while on.
+struct StubRec {
+  int kind;
+  bool fp32;
+  const void* in;
+  const void* out;
+};
+void stub_record(bool on);
+std::vector<StubRec> stub_records();

@@ -44,3 +44,13 @@ def test_every_failing_call_leaves_no_dangling_copy(harness):
     assert "bad 0" in r.stdout
     # every scenario ran every failure position on every thread
     assert r.stdout.count("every failure position tried") == 4 * 9
+
+
+def test_autotuner_times_on_scratch_iterates(harness):
+    """The autotuner's timed sweeps ping-pong between two scratch iterates
+    per precision, zero both afterwards and never write the iterate a solve
+    starts from."""
+    r = subprocess.run([harness, "tune"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, (r.stdout[-2000:] + "\n" + r.stderr[-4000:])
+    assert "tune ok" in r.stdout
+    assert r.stdout.count("on 2 buffers, zeroed 1 1, current iterate untouched 1") == 2
