@@ -77,6 +77,25 @@ def test_batch_equals_single_solver_bitwise():
         assert np.array_equal(b[name][1], u), name
 
 
+def test_batch_odd_sweeps_equals_single_solver_bitwise():
+    """Rounds of an odd number of sweeps (each one flips the members'
+    ping-pong parity) over a mix of shapes and precisions, launched group by
+    group, give bitwise the single-solver results with the same check
+    interval."""
+    from paper_1605_03228_amd.problem_io import make_solver
+    items = mix()[:3] + mix()[5:6]
+    together = solve_batch(items, 1e-11, sweeps=5)
+    for name, pr, prec in items:
+        print(f"[gpu] single solver {name} prec={prec} check_every=5", flush=True)
+        s = make_solver(pr, prec=prec, check_every=5)
+        res = s.solve(1e-11)
+        u = s.get_solution().reshape(s.sz["n_el"], -1).cpu().numpy()
+        s.close()
+        assert together[name][0]["status"] == 0, name
+        assert together[name][0]["iters"] == res["iters"], name
+        assert np.array_equal(together[name][1], u), name
+
+
 def _run_batch(items, tol, use_graphs, late=None, sweeps=16):
     from paper_1605_03228_amd import Batch
     from paper_1605_03228_amd.problem_io import make_solver
