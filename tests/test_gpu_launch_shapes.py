@@ -150,6 +150,28 @@ def test_own_tile_variant_solves(name, make):
     s.close()
 
 
+def test_own_tile_ragged_persistent_loop_matches_direct():
+    """At full scale the own-tile kernel's workgroups loop over several blocks
+    each; with 4092 blocks over 512 workgroups the last ones take a block
+    fewer (the loop's past-the-end exit).  Two sweeps from zero agree with the
+    direct kernel (5), a different MFMA schedule of the same operator, to
+    FP64 rounding."""
+    pr = w.transport_const((66, 64, 62), 3, (0.6, -0.48, 0.64), exact="u3")
+    out = {}
+    for wv in (7, 5):
+        print(f"[gpu] 66x64x62 p=3 shape {wv}", flush=True)
+        s = _solver(pr, block_waves=wv)
+        assert s.stats()["kernel_waves"] == wv
+        s.sweep(2)
+        out[wv] = s.get_solution().cpu().numpy()
+        s.close()
+    a, b = out[7], out[5]
+    assert np.isfinite(a).all()
+    r = np.abs(a - b).max() / np.abs(b).max()
+    print(f"  own vs direct: max rel diff {r:.2e}", flush=True)
+    assert r < 1e-13
+
+
 @pytest.mark.parametrize("waves", [3, 4, 5, 8])
 def test_bicgstab_on_every_cd_shared_shape(waves):
     """BiCGStab applies (I - T) through the launch shape it is given, the direct
