@@ -139,7 +139,7 @@ __device__ inline void face_step_to(const SweepArgs& a, int64_t blk, int f, int 
 // NW waves per SIMD are resident for NW <= 8 blocks per CU; ask the compiler
 // for that occupancy and no more, so it can keep a whole operator row in
 // flight instead of serialising the loads.
-template <typename T, int PDE, int DIM, int P, bool SHARED, int NW>
+template <typename T, int PDE, int DIM, int P, bool SHARED, int NW, bool NTS = false>
 __device__ __forceinline__ void sweep_block(const SweepArgs& a, int64_t blk, T* xs, double* red) {
   constexpr int N1 = P + 1, NP = ipow(N1, DIM), NFP = ipow(N1, DIM - 1), NF = 2 * DIM;
   constexpr int M = PdeTraits<PDE, DIM>::M, NLOC = M * NP, NIN = NF * NFP;
@@ -192,7 +192,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int64_t blk, T* 
 #pragma unroll
       for (int j = 0; j < NIN; ++j) acc += gv[j] * (XREG ? xr[j] : xs[j * kLanes + lane]);
     }
-    uout[o] = acc;
+    if constexpr (NTS)
+      __builtin_nontemporal_store(acc, &uout[o]);
+    else
+      uout[o] = acc;
     const double dd = (double)acc - (double)old, wt = a.wnorm[r];
     sd += wt * dd * dd;
     su += wt * (double)acc * (double)acc;
@@ -215,13 +218,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs& a, int64_t blk, T* 
   }
 }
 
-template <typename T, int PDE, int DIM, int P, bool SHARED, int NW>
+// NTS: u' written with the non-temporal hint (SweepArgs::stream_out).
+template <typename T, int PDE, int DIM, int P, bool SHARED, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW < 4 ? 4 : NW, 8)))
 void k_sweep(SweepArgs a) {
   constexpr int NIN = 2 * DIM * ipow(P + 1, DIM - 1);
   __shared__ T xs[NIN * kLanes];
   __shared__ double red[2 * NW];
-  sweep_block<T, PDE, DIM, P, SHARED, NW>(a, blockIdx.x, xs, red);
+  sweep_block<T, PDE, DIM, P, SHARED, NW, NTS>(a, blockIdx.x, xs, red);
 }
 
 // Batched sweep over the members of one bucket (same PDE, dimension, order,
@@ -465,19 +469,25 @@ hipError_t launch_mfma(int waves, const SweepArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T, int PDE, int DIM, int P, bool SHARED, bool NTS>
+hipError_t launch_vector(int waves, const SweepArgs& a, hipStream_t s) {
+  dim3 grid((unsigned)a.n_blk);
+  switch (waves) {
+    case 1: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 1, NTS>), grid, dim3(64), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 2, NTS>), grid, dim3(128), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 8, NTS>), grid, dim3(512), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 4, NTS>), grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
 template <typename T, int PDE, int DIM, int P, bool SHARED>
 hipError_t launch_one(int waves, const SweepArgs& a, hipStream_t s) {
   if constexpr (SHARED) {
     if (waves != 3) return launch_mfma<T, PDE, DIM, P>(waves, a, s);  // waves == 3: vector-FMA variant
   }
-  dim3 grid((unsigned)a.n_blk);
-  switch (waves) {
-    case 1: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 1>), grid, dim3(64), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 2>), grid, dim3(128), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 8>), grid, dim3(512), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_sweep<T, PDE, DIM, P, SHARED, 4>), grid, dim3(256), 0, s, a); break;
-  }
-  return hipGetLastError();
+  return a.stream_out ? launch_vector<T, PDE, DIM, P, SHARED, true>(waves, a, s)
+                      : launch_vector<T, PDE, DIM, P, SHARED, false>(waves, a, s);
 }
 
 template <typename T, int PDE, int DIM, int P, bool SHARED>

@@ -22,11 +22,11 @@ bool own_supported(int dim, int p) {
 // Workgroups resident at once (the runtime's occupancy for the instance's
 // registers and LDS, times the CUs; queried once per instance), the blocks
 // spread evenly over them.
-template <typename T, int P, int MASK>
+template <typename T, int P, int MASK, bool NTS>
 static int64_t own_grid(int64_t n_blk) {
   static const int64_t resident = [] {
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_own<T, P, MASK>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sweep_own<T, P, MASK, NTS>, 256, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -41,7 +41,12 @@ static int64_t own_grid(int64_t n_blk) {
 
 template <typename T, int P, int MASK>
 static hipError_t own_launch(const SweepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep_own<T, P, MASK>), dim3((unsigned)own_grid<T, P, MASK>(a.n_blk)), dim3(256), 0, s, a);
+  if (a.stream_out)
+    hipLaunchKernelGGL((k_sweep_own<T, P, MASK, true>), dim3((unsigned)own_grid<T, P, MASK, true>(a.n_blk)),
+                       dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sweep_own<T, P, MASK, false>), dim3((unsigned)own_grid<T, P, MASK, false>(a.n_blk)),
+                       dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

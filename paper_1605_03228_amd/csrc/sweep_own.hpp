@@ -241,7 +241,7 @@ __device__ __forceinline__ void own_fmap(const SweepArgs& a, int64_t blk, int le
   }
 }
 
-template <typename T, int P, int MASK, bool AREG = false>
+template <typename T, int P, int MASK, bool AREG = false, bool NTS = false>
 __device__ __forceinline__ void own_block(const SweepArgs& a, int64_t blk, int wt, const int (&sin)[3],
                                           const int (&sout)[3], const T* gs, const T (*ar)[OwnShape<T, P, MASK>::KT],
                                           const double* wl, double* red) {
@@ -326,7 +326,11 @@ __device__ __forceinline__ void own_block(const SweepArgs& a, int64_t blk, int w
       if (row < NLOC) {
         const T nv = acc[mt][r] + cp[mt][r];
         const double dd = (double)nv - (double)ut[mt][r], wn = wl[row];
-        uout[base + (int64_t)row * kLanes] = nv;
+        T* q = uout + base + (int64_t)row * kLanes;
+        if constexpr (NTS)
+          __builtin_nontemporal_store(nv, q);
+        else
+          *q = nv;
         sd += wn * dd * dd;
         su += wn * (double)nv * (double)nv;
       }
@@ -366,7 +370,8 @@ __device__ __forceinline__ void own_lds_barrier() {
 // partials alternate between two LDS slots, so wave 0's read of one block's
 // partials cannot meet another wave's write of the next block's), and the
 // next block's face map is in flight during the current block.
-template <typename T, int P, int MASK>
+// NTS: u' written with the non-temporal hint (SweepArgs::stream_out).
+template <typename T, int P, int MASK, bool NTS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OwnOcc<T>::W, OwnOcc<T>::W)))
 void k_sweep_own(SweepArgs a) {
   typedef OwnShape<T, P, MASK> Sh;
@@ -396,7 +401,7 @@ void k_sweep_own(SweepArgs a) {
     int nsin[3], nsout[3];
     own_fmap<P, MASK>(a, nxt, le, nsin, nsout);
     double* rb = red[i & 1];
-    own_block<T, P, MASK, AREG>(a, blk, wt, sin, sout, gs, ar, wl, rb);
+    own_block<T, P, MASK, AREG, NTS>(a, blk, wt, sin, sout, gs, ar, wl, rb);
     own_lds_barrier();
     if (tid == 0) {
       a.partials[2 * blk] = (rb[0] + rb[1]) + (rb[2] + rb[3]);
