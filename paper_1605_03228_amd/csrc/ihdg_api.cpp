@@ -668,7 +668,9 @@ hipError_t ihdg::launch_sweep(int pde, int dim, int p, bool fp32, bool shared, i
 // sweep has passed, and cached it would displace c_K and u^k lines that are.
 // Measured at 64^3, p = 3 (own-tile kernel): FP64 (402 MB) 88.4 against
 // 93.5 us; FP32 (201 MB, inside the cache) 54.6 against 50.0 us with the
-// hint, so it is not used there; at 80^3 neither precision changes.
+// hint, so it is not used there; at 80^3 neither precision changes.  The
+// LDS-staged matrix-core kernel on the 512^2, p = 3 diffusion sweep (302 MB):
+// 71.6-71.7 against 75.1-75.3 us, alternated on one GPU.
 static int stream_out(const ihdg_ctx* c, bool fp32) {
   return c->sweep_vals * (fp32 ? 4 : 8) > ihdg::kLastLevelCacheBytes ? 1 : 0;
 }

@@ -62,8 +62,9 @@ struct SweepArgs {
   int64_t n_el;         // elements (the last block's lanes past it are padding)
   double sqrt_phi;      // shallow water sqrt(Phi)
   int shape_arg;        // own-tile transport kernel: the outflow mask (bit a: high face of axis a)
-  int stream_out;       // 1: u' is written with the non-temporal hint (per-element and own-tile
-                        // kernels), set when the sweep's data exceed the last-level cache
+  int stream_out;       // 1: u' is written with the non-temporal hint (per-element, LDS-staged
+                        // matrix-core and own-tile kernels), set when the sweep's data exceed
+                        // the last-level cache
 };
 
 // The MI355X's last-level (Infinity) cache, in front of HBM.

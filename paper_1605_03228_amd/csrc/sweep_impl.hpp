@@ -318,7 +318,7 @@ __device__ __forceinline__ void load_smap(const SweepArgs& a, int64_t blk, int (
   }
 }
 
-template <typename T, int PDE, int DIM, int P, int NW>
+template <typename T, int PDE, int DIM, int P, int NW, bool NTS = false>
 __device__ __forceinline__ void mfma_block(const SweepArgs& a, int64_t blk,
                                            const T (&av)[MfmaShape<T, PDE, DIM, P, NW>::MTW][MfmaShape<T, PDE, DIM, P, NW>::KT],
                                            const int (&smap)[MfmaShape<T, PDE, DIM, P, NW>::PPT], T* xs, double* red) {
@@ -394,7 +394,10 @@ __device__ __forceinline__ void mfma_block(const SweepArgs& a, int64_t blk,
           const int64_t o = (blk * NLOC + row) * kLanes + nt * 16 + li;
           const T nv = acc[j][r] + cpre[j][r];
           const double dd = (double)nv - (double)upre[j][r], wt = a.wnorm[row];
-          uout[o] = nv;
+          if constexpr (NTS)
+            __builtin_nontemporal_store(nv, &uout[o]);
+          else
+            uout[o] = nv;
           sd += wt * dd * dd;
           su += wt * (double)nv * (double)nv;
         }
@@ -419,7 +422,8 @@ __device__ __forceinline__ void mfma_block(const SweepArgs& a, int64_t blk,
   }
 }
 
-template <typename T, int PDE, int DIM, int P, int NW>
+// NTS: u' written with the non-temporal hint (SweepArgs::stream_out).
+template <typename T, int PDE, int DIM, int P, int NW, bool NTS>
 __global__ __launch_bounds__(64 * NW) void k_sweep_mfma(SweepArgs a) {
   typedef MfmaShape<T, PDE, DIM, P, NW> Sh;
   __shared__ T xs[Sh::KT * 4 * Sh::S];
@@ -434,7 +438,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_mfma(SweepArgs a) {
 #pragma unroll
     for (int pp = 0; pp < Sh::PPT; ++pp) cur[pp] = smap[pp];
     load_smap<T, PDE, DIM, P, NW>(a, blk + gridDim.x, smap);  // next block's face map, in flight meanwhile
-    mfma_block<T, PDE, DIM, P, NW>(a, blk, av, cur, xs, red);
+    mfma_block<T, PDE, DIM, P, NW, NTS>(a, blk, av, cur, xs, red);
     __syncthreads();  // xs and red are reused by the next block
   }
 }
@@ -461,10 +465,17 @@ template <typename T, int PDE, int DIM, int P>
 hipError_t launch_mfma(int waves, const SweepArgs& a, hipStream_t s) {
   // persistent: a few workgroups per CU loop over the 64-element blocks
   const int64_t g = a.n_blk < 2048 ? a.n_blk : 2048;
+  const dim3 grid((unsigned)g);
   if (waves == 8) {
-    hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 8>), dim3((unsigned)g), dim3(512), 0, s, a);
+    if (a.stream_out)
+      hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 8, true>), grid, dim3(512), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 8, false>), grid, dim3(512), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 4>), dim3((unsigned)g), dim3(256), 0, s, a);
+    if (a.stream_out)
+      hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 4, true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_sweep_mfma<T, PDE, DIM, P, 4, false>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();
 }
