@@ -172,6 +172,32 @@ def test_own_tile_ragged_persistent_loop_matches_direct():
     assert r < 1e-13
 
 
+@pytest.mark.parametrize("name,make,waves", [
+    ("transport_66x64x62_p3", lambda: w.transport_const((66, 64, 62), 3, (0.6, -0.48, 0.64), exact="u3"), 4),
+    ("transport_66x64x62_p3", lambda: w.transport_const((66, 64, 62), 3, (0.6, -0.48, 0.64), exact="u3"), 8),
+    ("elliptic_512x512_p3", lambda: w.cd_elliptic((512, 512), 3, gamma=1.0, nu=1.0), 4),
+], ids=["transport3d_w4", "transport3d_w8", "elliptic512_w4"])
+def test_lds_staged_kernel_beyond_the_cache_matches_direct(name, make, waves):
+    """Above 256 MB of sweep data (402 MB and 302 MB here) the LDS-staged
+    matrix-core kernel writes its output with the non-temporal hint.  Two FP64
+    sweeps from zero agree with the direct kernel (5), another MFMA schedule of
+    the same operator, to FP64 rounding."""
+    pr = make()
+    out = {}
+    for wv in (waves, 5):
+        print(f"[gpu] {name} shape {wv}", flush=True)
+        s = _solver(pr, block_waves=wv)
+        assert s.stats()["kernel_waves"] == wv
+        s.sweep(2)
+        out[wv] = s.get_solution().cpu().numpy()
+        s.close()
+    a, b = out[waves], out[5]
+    assert np.isfinite(a).all()
+    r = np.abs(a - b).max() / np.abs(b).max()
+    print(f"  shape {waves} vs direct: max rel diff {r:.2e}", flush=True)
+    assert r < 1e-12
+
+
 @pytest.mark.parametrize("waves", [3, 4, 5, 8])
 def test_bicgstab_on_every_cd_shared_shape(waves):
     """BiCGStab applies (I - T) through the launch shape it is given, the direct
